@@ -1,0 +1,206 @@
+/*
+ * adr.h -- C ABI of the MI355X (gfx950) ILU(0)-preconditioned BiCGSTAB solver
+ * for the 2-D steady advection-diffusion problem of Datta & Carrasco Heres,
+ * arXiv:1308.5215:
+ *
+ *     eps (u_xx + u_yy) + a(x,y) u_x + b(x,y) u_y = f   on [0,X] x [0,Y],
+ *     a = 1 + x^2,  b = X exp(-y),                      (Section 2, eq. (1))
+ *
+ * with Dirichlet data on x = 0 and y = 0 and either Dirichlet or Neumann data
+ * on x = X and y = Y, taken from the manufactured solution
+ * u = exp(-x/X) (1 - exp(-y/Y)) y (Sections 2-3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.   nx * ny interior unknowns; unknown (i, j), 0 <= i < nx, 0 <= j < ny,
+ *         lives at x = (i+1) dx, y = (j+1) dy, dx = X/(nx+1), dy = Y/(ny+1),
+ *         and is stored at k = j*nx + i (x fastest; the lexicographic order of
+ *         the paper's assembly).  nx = m-1, ny = n-1 for the paper's m, n
+ *         intervals.
+ * Vectors. FP64, length nx*ny, in that order.  "_dev" pointers are device
+ *         pointers on the current HIP device; "_host" pointers are host
+ *         memory.  The caller owns every pointer it passes; the library
+ *         copies what it keeps and never frees caller memory.
+ * Streams. Every call is issued on the stream given to adr_assemble (NULL =
+ *         the default stream) and has completed on return.
+ * Errors.  Negative adr_status values are call errors (nothing or only part
+ *         of the work was done: check adr_last_error()); non-negative values
+ *         are outcomes.  Argument errors are detected before any device work.
+ * Threads. A problem handle must not be used by two threads at once.
+ */
+#ifndef ADR_H
+#define ADR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADR_OK = 0,
+  ADR_ERR_ARG = -1,       /* invalid argument (see adr_last_error)          */
+  ADR_ERR_NOMEM = -2,     /* device allocation failed                       */
+  ADR_ERR_DEVICE = -3,    /* HIP runtime error or device-side fault report  */
+  ADR_ERR_STATE = -4,     /* call out of order (e.g. solve before ilu0)     */
+  ADR_MAXIT = 1,          /* maxit passes done without convergence          */
+  ADR_BREAKDOWN_RHO = 2,  /* rho = r^.r = 0 at the start of a pass          */
+  ADR_OMEGA_ZERO = 3,     /* omega = 0 (the method's own stop)              */
+  ADR_ZERO_PIVOT = 4,     /* ILU(0) met a zero or non-finite pivot          */
+  ADR_NONFINITE = 5       /* a scalar of the iteration became Inf or NaN    */
+} adr_status;
+
+typedef enum {
+  ADR_UPWIND = 0,   /* the paper's "hybrid" scheme: centred second differences,
+                       backward first differences (Section 4)                */
+  ADR_CENTERED = 1  /* centred first and second differences (Section 4)     */
+} adr_scheme;
+
+typedef enum {
+  ADR_BC_DIRICHLET = 0,  /* Dirichlet on all four sides                     */
+  ADR_BC_NEUMANN_XY = 1  /* Dirichlet on x = 0, y = 0; Neumann on x = X and
+                            y = Y, closed by the one-sided difference of the
+                            paper's Neumann assembly routines               */
+} adr_bc;
+
+typedef enum {
+  ADR_FP64 = 0,          /* factors and sweeps in FP64                      */
+  ADR_FP32_FACTORS = 1,  /* ILU(0) factors stored in FP32, sweep arithmetic
+                            in FP64                                          */
+  ADR_FP32_SWEEPS = 2    /* ILU(0) factors stored in FP32 and the triangular
+                            sweeps computed in FP32; SpMV, inner products,
+                            scalars and the stopping test stay FP64         */
+} adr_precision;
+
+typedef struct adr_problem adr_problem;   /* opaque, library-owned */
+
+typedef struct {
+  int32_t status;       /* adr_status of the solve                               */
+  int32_t iters;        /* loop passes started; a half-step exit counts         */
+  int32_t hist_len;     /* valid entries in hist_l2 / hist_max                  */
+  int32_t half_step;    /* 1 if the solve ended on the ||s|| test               */
+  double bnorm;         /* ||b||_2                                               */
+  double true_relres;   /* ||b - A x||_2 / ||b||_2 recomputed at exit            */
+  double solve_ms;      /* device time of the iteration (events on the stream)  */
+} adr_solve_info;
+
+/* ---------------------------------------------------------------------------
+ * adr_assemble -- Section 4 discretisation into five diagonals.
+ *
+ * Builds, on the device, S (k-nx), W (k-1), C (k), E (k+1), N (k+nx) and the
+ * right-hand side of every interior equation multiplied by dx^2 dy^2:
+ *   upwind:   S = eps dx^2 - b dx^2 dy,        W = eps dy^2 - a dx dy^2,
+ *             C = -2 eps (dx^2 + dy^2) + a dx dy^2 + b dx^2 dy,
+ *             E = eps dy^2,                   N = eps dx^2;
+ *   centered: S = eps dx^2 - b dx^2 dy / 2,    W = eps dy^2 - a dx dy^2 / 2,
+ *             C = -2 eps (dx^2 + dy^2),
+ *             E = eps dy^2 + a dx dy^2 / 2,   N = eps dx^2 + b dx^2 dy / 2;
+ *   rhs = f dx^2 dy^2 minus boundary couplings times boundary data; Neumann:
+ *   C += E (x = X edge), C += N (y = Y edge), rhs -= E dx g_x, rhs -= N dy g_y.
+ * Couplings to boundary nodes are stored as 0.
+ * f is the manufactured forcing of Section 3; if field_dev != NULL (nx*ny
+ * FP64 values), f = f_man + amp * max|f_man| * field (max over interior
+ * nodes), the forcing perturbation of a random-field workload.
+ * eps, X, Y > 0; nx, ny >= 1; nx*ny <= 2^31 - 1.
+ * stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL.
+ * On success *out receives a new problem handle (free with adr_destroy).
+ * ------------------------------------------------------------------------- */
+adr_status adr_assemble(double eps, double X, double Y, int32_t nx, int32_t ny,
+                        int32_t scheme, int32_t bc,
+                        const double *field_dev, double amp,
+                        void *stream, adr_problem **out);
+
+/* ---------------------------------------------------------------------------
+ * adr_ilu0 -- ILU(0) of Section 5.1 (Saad): the incomplete LU factorisation
+ * whose sparsity pattern is that of A.  For the five-point matrix the factor
+ * L is unit lower with lw at (k,k-1) and ls at (k,k-nx), U = diag(d) + the
+ * E, N diagonals of A, and the pivots follow
+ *     d_k = C_k - lw_k E_{k-1} - ls_k N_{k-nx},
+ *     lw_k = W_k / d_{k-1},  ls_k = S_k / d_{k-nx}
+ * (computed as invd = 1/d, lw = W*invd_{k-1}, ls = S*invd_{k-nx},
+ *  d = fma(-ls, N_{k-nx}, fma(-lw, E_{k-1}, C))), swept over anti-diagonals.
+ * precision selects the storage/arithmetic of the sweeps that apply M^{-1}
+ * (adr_precision).  Returns ADR_ZERO_PIVOT if some pivot is 0 or not finite;
+ * then *bad_index (if not NULL) receives the first such k in lexicographic
+ * order and the problem cannot be solved.  Otherwise *bad_index = -1.
+ * ------------------------------------------------------------------------- */
+adr_status adr_ilu0(adr_problem *p, int32_t precision, int64_t *bad_index);
+
+/* ---------------------------------------------------------------------------
+ * adr_bicgstab_solve -- right-preconditioned BiCGSTAB of Section 5.2 with
+ * M = L U from adr_ilu0.
+ *   r0 = b - A x0, r^ = r0; per pass i: rho = r^.r (ADR_BREAKDOWN_RHO if 0);
+ *   p = r (i = 1) or r + beta (p - omega v), beta = (rho_i/rho_{i-1})(alpha/omega);
+ *   p^ = M^{-1} p; v = A p^; alpha = rho / r^.v; s = r - alpha v;
+ *   if ||s||_2 < tol ||b||_2: x += alpha p^ and stop (half step);
+ *   z = M^{-1} s; t = A z; omega = t.s / t.t; x += alpha p^ + omega z;
+ *   r = s - omega t; stop if ||r||_2 < tol ||b||_2; stop if omega = 0.
+ * Inner products are double-double accumulations rounded once to FP64, so the
+ * result does not depend on the summation order.  If ||r0|| already passes
+ * the test no pass is made; b = 0 gives x = 0.
+ * x0_dev: initial guess (device, nx*ny) or NULL for zero.
+ * x_dev:  output (device, nx*ny); may equal x0_dev.
+ * hist_l2_host, hist_max_host: NULL or host arrays of maxit+1 entries:
+ *   entry 0 = ||r0||, entry i = ||r_i|| after pass i (the recursively updated
+ *   residual), or ||s|| at a half-step exit; 2-norm and max-norm.
+ * info: optional summary.  tol >= 0, maxit >= 0.
+ * Returns the solve status (ADR_OK, ADR_MAXIT, ADR_BREAKDOWN_RHO,
+ * ADR_OMEGA_ZERO, ADR_NONFINITE) or a call error; x_dev holds the last
+ * iterate in every outcome.
+ * ------------------------------------------------------------------------- */
+adr_status adr_bicgstab_solve(adr_problem *p, double tol, int32_t maxit,
+                              const double *x0_dev, double *x_dev,
+                              double *hist_l2_host, double *hist_max_host,
+                              adr_solve_info *info);
+
+/* Release every device resource of the problem (NULL is a no-op). */
+void adr_destroy(adr_problem *p);
+
+/* ---------------------------------------------------------------------------
+ * Inspection and single-step entry points (the same kernels the solve uses).
+ * ------------------------------------------------------------------------- */
+
+/* Copy the assembled diagonals and rhs to host arrays of nx*ny entries
+ * (any may be NULL). */
+adr_status adr_get_dia(const adr_problem *p, double *S, double *W, double *C,
+                       double *E, double *N, double *rhs);
+
+/* Replace the assembled diagonals and rhs from host arrays (all six
+ * required); invalidates the factorisation. */
+adr_status adr_set_dia(adr_problem *p, const double *S, const double *W,
+                       const double *C, const double *E, const double *N,
+                       const double *rhs);
+
+/* Copy the FP64 factors (lw, ls, invd; any may be NULL) to host arrays. */
+adr_status adr_get_factors(const adr_problem *p, double *lw, double *ls, double *invd);
+
+/* v = A x (device vectors), the five-point product with out-of-grid
+ * neighbours contributing 0: fma(N,x_n, fma(E,x_e, fma(W,x_w, fma(S,x_s, C x)))). */
+adr_status adr_spmv(adr_problem *p, const double *x_dev, double *v_dev);
+
+/* z = M^{-1} q = U^{-1} L^{-1} q with the current factors (device vectors):
+ *   y_k = fma(-ls, y_{k-nx}, fma(-lw, y_{k-1}, q_k)),
+ *   z_k = fma(-N, z_{k+nx}, fma(-E, z_{k+1}, y_k)) * invd_k. */
+adr_status adr_precond(adr_problem *p, const double *q_dev, double *z_dev);
+
+/* Double-double inner product of two device vectors of length n, rounded to
+ * FP64, written to *out (host). */
+adr_status adr_dot(const double *x_dev, const double *y_dev, int64_t n, void *stream,
+                   double *out);
+
+/* Bytes of device memory the problem holds (after ilu0 / solve buffers). */
+size_t adr_device_bytes(const adr_problem *p);
+
+/* Sweep geometry in use: rows per strip (R) for the wavefront kernels, or 0
+ * to pick automatically.  For tuning and tests. */
+adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
+
+const char *adr_status_str(int32_t status);
+/* Message of the last call error on this thread ("" if none). */
+const char *adr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADR_H */

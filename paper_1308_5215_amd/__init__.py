@@ -1,0 +1,181 @@
+"""MI355X-native ILU(0)-preconditioned BiCGSTAB for the 2-D advection-diffusion
+problem of Datta & Carrasco Heres (arXiv:1308.5215).
+
+Thin Python layer over the C ABI of ``libadr.so`` (include/adr.h): PyTorch
+supplies device memory and the stream; every step of the solver runs in the
+library's HIP kernels.
+
+    import paper_1308_5215_amd as adr
+    prob = adr.assemble(eps=0.1, X=1, Y=1, nx=64, ny=64, scheme="upwind", bc="dirichlet")
+    prob.ilu0()
+    res = prob.solve(tol=1e-10, maxit=1000)      # res.x is a CUDA tensor
+"""
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import (OK, MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE, UPWIND, CENTERED,
+                   DIRICHLET, NEUMANN_XY, FP64, FP32_FACTORS, FP32_SWEEPS, AdrError)
+
+__all__ = ["assemble", "Problem", "SolveResult", "dot", "AdrError", "OK", "MAXIT", "BREAKDOWN_RHO",
+           "OMEGA_ZERO", "ZERO_PIVOT", "NONFINITE", "UPWIND", "CENTERED", "DIRICHLET", "NEUMANN_XY",
+           "FP64", "FP32_FACTORS", "FP32_SWEEPS"]
+
+_SCHEMES = {"upwind": UPWIND, "hybrid": UPWIND, "centered": CENTERED, UPWIND: UPWIND, CENTERED: CENTERED}
+_BCS = {"dirichlet": DIRICHLET, "neumann": NEUMANN_XY, DIRICHLET: DIRICHLET, NEUMANN_XY: NEUMANN_XY}
+_PREC = {"fp64": FP64, "fp32_factors": FP32_FACTORS, "fp32_sweeps": FP32_SWEEPS,
+         FP64: FP64, FP32_FACTORS: FP32_FACTORS, FP32_SWEEPS: FP32_SWEEPS}
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f64(t, n, name):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError("%s must be a CUDA float64 tensor" % name)
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError("%s must be contiguous with %d elements" % (name, n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_ptr(a):
+    return a.ctypes.data_as(_D)
+
+
+@dataclass
+class SolveResult:
+    x: object            # CUDA float64 tensor (nx*ny)
+    status: int
+    iters: int
+    half_step: bool
+    hist_l2: np.ndarray
+    hist_max: np.ndarray
+    bnorm: float
+    true_relres: float
+    solve_ms: float
+
+    @property
+    def amplification(self):
+        """||r^{k+1}|| / ||r^k|| (the paper's amplification factor, Section 6.5)."""
+        h = self.hist_l2
+        return h[1:] / h[:-1]
+
+
+class Problem:
+    """One assembled five-point system on the current device."""
+
+    def __init__(self, handle, eps, X, Y, nx, ny, scheme, bc, stream):
+        self._h = handle
+        self.eps, self.X, self.Y, self.nx, self.ny = eps, X, Y, nx, ny
+        self.scheme, self.bc = scheme, bc
+        self.n = nx * ny
+        self._stream = stream
+        self.precision = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().adr_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    # -- the three calls of the method --
+    def ilu0(self, precision="fp64"):
+        prec = _PREC[precision]
+        bad = ctypes.c_int64(-1)
+        st = _lib.check(_lib.load().adr_ilu0(self._h, prec, ctypes.byref(bad)))
+        if st == ZERO_PIVOT:
+            raise AdrError(st, "zero or non-finite pivot at unknown %d" % bad.value)
+        self.precision = prec
+        return self
+
+    def solve(self, tol=1e-10, maxit=1000, x0=None, out=None):
+        torch = _torch()
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        xp = _dev_f64(x, self.n, "out")
+        x0p = None if x0 is None else _dev_f64(x0, self.n, "x0")
+        h2 = np.zeros(maxit + 1)
+        hm = np.zeros(maxit + 1)
+        info = _lib.SolveInfo()
+        st = _lib.check(_lib.load().adr_bicgstab_solve(self._h, float(tol), int(maxit), x0p, xp,
+                                                        _host_ptr(h2), _host_ptr(hm), ctypes.byref(info)))
+        hl = info.hist_len
+        return SolveResult(x, st, info.iters, bool(info.half_step), h2[:hl].copy(), hm[:hl].copy(),
+                           info.bnorm, info.true_relres, info.solve_ms)
+
+    # -- inspection and single steps --
+    def get_dia(self):
+        arrs = [np.zeros(self.n) for _ in range(6)]
+        _lib.check(_lib.load().adr_get_dia(self._h, *[_host_ptr(a) for a in arrs]))
+        return dict(zip(("S", "W", "C", "E", "N", "rhs"), arrs))
+
+    def set_dia(self, S, W, C, E, N, rhs):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (S, W, C, E, N, rhs)]
+        for a in arrs:
+            if a.size != self.n:
+                raise ValueError("each array needs %d entries" % self.n)
+        _lib.check(_lib.load().adr_set_dia(self._h, *[_host_ptr(a) for a in arrs]))
+        self.precision = None
+
+    def get_factors(self):
+        arrs = [np.zeros(self.n) for _ in range(3)]
+        _lib.check(_lib.load().adr_get_factors(self._h, *[_host_ptr(a) for a in arrs]))
+        return dict(zip(("lw", "ls", "invd"), arrs))
+
+    def spmv(self, x, out=None):
+        torch = _torch()
+        v = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _lib.check(_lib.load().adr_spmv(self._h, _dev_f64(x, self.n, "x"), _dev_f64(v, self.n, "out")))
+        return v
+
+    def precond(self, q, out=None):
+        torch = _torch()
+        z = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _lib.check(_lib.load().adr_precond(self._h, _dev_f64(q, self.n, "q"), _dev_f64(z, self.n, "out")))
+        return z
+
+    def set_sweep_rows(self, rows):
+        _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
+
+    @property
+    def device_bytes(self):
+        return int(_lib.load().adr_device_bytes(self._h))
+
+
+def assemble(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet", field=None, amp=0.0, stream=None):
+    """Section 4 assembly on the device; see adr_assemble in include/adr.h.
+    field: optional CUDA float64 tensor (nx*ny) added to the manufactured
+    forcing with amplitude amp * max|f_man|."""
+    torch = _torch()
+    L = _lib.load()
+    sch, b = _SCHEMES[scheme], _BCS[bc]
+    fp = None if field is None else _dev_f64(field, int(nx) * int(ny), "field")
+    sh = _stream_handle(stream)
+    h = ctypes.c_void_p()
+    _lib.check(L.adr_assemble(float(eps), float(X), float(Y), int(nx), int(ny), sch, b, fp, float(amp),
+                              sh, ctypes.byref(h)))
+    return Problem(h, float(eps), float(X), float(Y), int(nx), int(ny), sch, b, stream)
+
+
+def dot(x, y, stream=None):
+    """Double-double inner product of two CUDA float64 vectors (adr_dot)."""
+    n = x.numel()
+    out = ctypes.c_double(0.0)
+    _lib.check(_lib.load().adr_dot(_dev_f64(x, n, "x"), _dev_f64(y, n, "y"), n, _stream_handle(stream),
+                                   ctypes.byref(out)))
+    return out.value

@@ -1,0 +1,88 @@
+"""ctypes binding of ``libadr.so`` (include/adr.h).  Argument marshalling
+only: every step of the solver runs in the library's HIP kernels.  There is
+no fallback: if the library is missing or does not load, importing this
+module raises."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadr.so")
+
+# Names and numbering of include/adr.h
+OK, ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_STATE = 0, -1, -2, -3, -4
+MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE = 1, 2, 3, 4, 5
+UPWIND, CENTERED = 0, 1
+DIRICHLET, NEUMANN_XY = 0, 1
+FP64, FP32_FACTORS, FP32_SWEEPS = 0, 1, 2
+
+EXPORTS = [
+    "adr_assemble", "adr_ilu0", "adr_bicgstab_solve", "adr_destroy", "adr_get_dia", "adr_set_dia",
+    "adr_get_factors", "adr_spmv", "adr_precond", "adr_dot", "adr_device_bytes",
+    "adr_set_sweep_rows", "adr_status_str", "adr_last_error",
+]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("hist_len", ctypes.c_int32),
+                ("half_step", ctypes.c_int32), ("bnorm", ctypes.c_double),
+                ("true_relres", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises OSError if it is absent or broken)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError("libadr.so is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python paper_1308_5215_amd/build.py`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    D = ctypes.POINTER(ctypes.c_double)
+    L.adr_assemble.restype = ctypes.c_int
+    L.adr_assemble.argtypes = [f64, f64, f64, i32, i32, i32, i32, P, f64, P, ctypes.POINTER(P)]
+    L.adr_ilu0.restype = ctypes.c_int
+    L.adr_ilu0.argtypes = [P, i32, ctypes.POINTER(i64)]
+    L.adr_bicgstab_solve.restype = ctypes.c_int
+    L.adr_bicgstab_solve.argtypes = [P, f64, i32, P, P, D, D, ctypes.POINTER(SolveInfo)]
+    L.adr_destroy.restype = None
+    L.adr_destroy.argtypes = [P]
+    L.adr_get_dia.restype = ctypes.c_int
+    L.adr_get_dia.argtypes = [P] + [D] * 6
+    L.adr_set_dia.restype = ctypes.c_int
+    L.adr_set_dia.argtypes = [P] + [D] * 6
+    L.adr_get_factors.restype = ctypes.c_int
+    L.adr_get_factors.argtypes = [P] + [D] * 3
+    L.adr_spmv.restype = ctypes.c_int
+    L.adr_spmv.argtypes = [P, P, P]
+    L.adr_precond.restype = ctypes.c_int
+    L.adr_precond.argtypes = [P, P, P]
+    L.adr_dot.restype = ctypes.c_int
+    L.adr_dot.argtypes = [P, P, i64, P, D]
+    L.adr_device_bytes.restype = ctypes.c_size_t
+    L.adr_device_bytes.argtypes = [P]
+    L.adr_set_sweep_rows.restype = ctypes.c_int
+    L.adr_set_sweep_rows.argtypes = [P, i32]
+    L.adr_status_str.restype = ctypes.c_char_p
+    L.adr_status_str.argtypes = [i32]
+    L.adr_last_error.restype = ctypes.c_char_p
+    L.adr_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+class AdrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (load().adr_status_str(status).decode(), status, msg))
+        self.status = status
+
+
+def check(status):
+    """Raise AdrError on a call error (negative status); return outcomes."""
+    if status < 0:
+        raise AdrError(status, load().adr_last_error().decode())
+    return status

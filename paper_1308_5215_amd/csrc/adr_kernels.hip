@@ -1,0 +1,598 @@
+// HIP kernels for gfx950: assembly, five-point SpMV, double-double inner
+// products, the BiCGSTAB vector updates with their single-block finalize
+// steps, and the anti-diagonal wavefront kernels (ILU(0) factorisation and
+// the L / U triangular sweeps).
+//
+// Floating point: compiled with -ffp-contract=off; every fused multiply-add
+// is an explicit fma().  Every per-point formula below is the fixed
+// evaluation order stated in include/adr.h, so results do not depend on the
+// launch geometry.
+#include <hip/hip_runtime.h>
+
+#include "adr_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace adr {
+
+constexpr int BLK = 256;     // threads per block of the streaming kernels
+constexpr int MAXSLOT = 4;   // partial-sum slots per block (3 dd sums + 1 max)
+
+// ---------------------------------------------------------------------------
+// Double-double arithmetic: TwoSum (Knuth), FastTwoSum (Dekker), TwoProd by
+// fma, and the accurate double-word addition of Joldes, Muller & Popescu
+// (ACM TOMS 2017).  An inner product accumulated this way and rounded once is
+// the exact inner product rounded to nearest up to O(n u^2) sum|x_k y_k|, so
+// it does not depend on how the sum is split over blocks and lanes.
+// ---------------------------------------------------------------------------
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void fast_two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  e = b - (s - a);
+}
+__device__ __forceinline__ dd dd_add(dd x, dd y) {
+  double sh, sl, th, tl, vh, vl;
+  two_sum(x.hi, y.hi, sh, sl);
+  two_sum(x.lo, y.lo, th, tl);
+  const double c = sl + th;
+  fast_two_sum(sh, c, vh, vl);
+  const double w = tl + vl;
+  dd z;
+  fast_two_sum(vh, w, z.hi, z.lo);
+  return z;
+}
+__device__ __forceinline__ dd dd_prod(double a, double b) {
+  const double p = a * b;
+  return dd{p, fma(a, b, -p)};
+}
+__device__ __forceinline__ double nanmax(double a, double b) {
+  return (a != a) ? a : ((b != b) ? b : (a > b ? a : b));
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+__device__ __forceinline__ dd wave_reduce_dd(dd v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    dd o{shfl_xor_d(v.hi, m), shfl_xor_d(v.lo, m)};
+    v = dd_add(v, o);
+  }
+  return v;
+}
+__device__ __forceinline__ double wave_reduce_max(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = nanmax(v, shfl_xor_d(v, m));
+  return v;
+}
+
+// Reduce NS dd values and one max over a block of BLK threads; thread 0
+// writes them to partials[slot * nblk + block].
+template <int NS, bool MAX>
+__device__ __forceinline__ void block_partials(const dd (&v)[NS > 0 ? NS : 1], double mx,
+                                               double2 *partials, int nblk, int bid) {
+  __shared__ dd sh[NS > 0 ? NS : 1][BLK / 64];
+  __shared__ double shm[BLK / 64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    dd r = wave_reduce_dd(v[q]);
+    if (l == 0) sh[q][w] = r;
+  }
+  if (MAX) {
+    double m = wave_reduce_max(mx);
+    if (l == 0) shm[w] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      dd r = sh[q][0];
+#pragma unroll
+      for (int u = 1; u < BLK / 64; ++u) r = dd_add(r, sh[q][u]);
+      partials[(size_t)q * nblk + bid] = make_double2(r.hi, r.lo);
+    }
+    if (MAX) {
+      double m = shm[0];
+#pragma unroll
+      for (int u = 1; u < BLK / 64; ++u) m = nanmax(m, shm[u]);
+      partials[(size_t)3 * nblk + bid] = make_double2(m, 0.0);
+    }
+  }
+}
+
+// Single-block fixed-order combine of the per-block partials of one slot.
+__device__ dd combine_dd(const double2 *part, int nblk) {
+  __shared__ dd sh[BLK / 64];
+  dd acc{0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += BLK) {
+    const double2 q = part[b];
+    acc = dd_add(acc, dd{q.x, q.y});
+  }
+  dd r = wave_reduce_dd(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
+  __syncthreads();
+  dd out = sh[0];
+  for (int u = 1; u < BLK / 64; ++u) out = dd_add(out, sh[u]);
+  __syncthreads();
+  return out;  // same value in every thread
+}
+__device__ double combine_max(const double2 *part, int nblk) {
+  __shared__ double sh[BLK / 64];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += BLK) acc = nanmax(acc, part[b].x);
+  double r = wave_reduce_max(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
+  __syncthreads();
+  double out = sh[0];
+  for (int u = 1; u < BLK / 64; ++u) out = nanmax(out, sh[u]);
+  __syncthreads();
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Launch geometry helpers.
+// ---------------------------------------------------------------------------
+
+// Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8);
+// give each XCD one contiguous range of tiles so that the rows above and
+// below a tile (the +-nx neighbours of the stencil) sit in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nblk) {
+  const int x = bid & 7, q = bid >> 3;
+  const int per = nblk >> 3, rem = nblk & 7;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+  const uint32_t t = __umulhi(n, f.m);
+  return (t + n) >> f.s;
+}
+
+__device__ __forceinline__ double spmv_point(const Dia &A, const double *__restrict__ x, int k, int i,
+                                             int j, int nx, int ny) {
+  const double xs = (j > 0) ? x[k - nx] : 0.0;
+  const double xw = (i > 0) ? x[k - 1] : 0.0;
+  const double xe = (i < nx - 1) ? x[k + 1] : 0.0;
+  const double xn = (j < ny - 1) ? x[k + nx] : 0.0;
+  double t = A.C[k] * x[k];
+  t = fma(A.S[k], xs, t);
+  t = fma(A.W[k], xw, t);
+  t = fma(A.E[k], xe, t);
+  t = fma(A.N[k], xn, t);
+  return t;
+}
+
+#define ADR_BLOCK_RANGE(g, beg, end)                 \
+  const int tile_ = xcd_tile(blockIdx.x, (g).nblk); \
+  const int beg = tile_ * (g).chunk;                 \
+  const int end = min(beg + (g).chunk, (g).n)
+
+// ---------------------------------------------------------------------------
+// Fill kernels.
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double *p, int64_t n, double v) {
+  for (int64_t k = (int64_t)blockIdx.x * BLK + threadIdx.x; k < n; k += (int64_t)gridDim.x * BLK) p[k] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+  for (int64_t k = (int64_t)blockIdx.x * BLK + threadIdx.x; k < n; k += (int64_t)gridDim.x * BLK) p[k] = v;
+}
+__global__ void k_fill_u32(unsigned *p, int64_t n, unsigned v) {
+  for (int64_t k = (int64_t)blockIdx.x * BLK + threadIdx.x; k < n; k += (int64_t)gridDim.x * BLK) p[k] = v;
+}
+static int fill_blocks(int64_t n) {
+  int64_t b = (n + BLK - 1) / BLK;
+  return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(fill_blocks(n)), dim3(BLK), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(fill_blocks(n)), dim3(BLK), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(BLK), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Assembly (Section 4).  The 1-D tables (coordinates, a_i, b_j, the
+// exponentials and the boundary data) come from the host; every per-point
+// value is formed here in the documented order.
+// ---------------------------------------------------------------------------
+
+// Manufactured forcing, Section 3, three-term form with exp(-(x/X + y/Y))
+// taken as exp(-x/X) exp(-y/Y).
+__device__ __forceinline__ double f_point(double eps, double X, double Y, double x, double y,
+                                          double a, double ex, double ey, double eb) {
+  const double X2 = X * X, Y2 = Y * Y;
+  const double exy = ex * ey;
+  const double t1 = eps * ((y / X2) * ex + ((2.0 / Y - y / Y2) - y / X2) * exy);
+  const double ya = (y * a) / X;
+  const double t2 = ex * (X * eb - ya);
+  const double t3 = exy * ((ya - X * eb) + ((X / Y) * y) * eb);
+  return (t1 + t2) + t3;
+}
+
+__global__ __launch_bounds__(BLK) void k_fmax(AssembleArgs a, Stream1D g, FastDiv fd) {
+  ADR_BLOCK_RANGE(g, beg, end);
+  double m = 0.0;
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, fd), i = k - j * a.nx;
+    const double f = f_point(a.eps, a.X, a.Y, a.xi[i], a.yj[j], a.ai[i], a.exi[i], a.eyj[j], a.ebj[j]);
+    m = nanmax(m, fabs(f));
+  }
+  dd none[1] = {dd{0.0, 0.0}};
+  block_partials<0, true>(none, m, a.partials, g.nblk, blockIdx.x);
+}
+__global__ __launch_bounds__(BLK) void k_fmax_fin(AssembleArgs a, Stream1D g) {
+  const double m = combine_max(a.partials + (size_t)3 * g.nblk, g.nblk);
+  if (threadIdx.x == 0) *a.fmax = m;
+}
+
+__global__ __launch_bounds__(BLK) void k_assemble(AssembleArgs a, Stream1D g, FastDiv fd) {
+  ADR_BLOCK_RANGE(g, beg, end);
+  const int nx = a.nx, ny = a.ny;
+  const double dx2 = a.dx * a.dx, dy2 = a.dy * a.dy;
+  const double cx = a.eps * dy2, cy = a.eps * dx2;
+  const double gx = a.dx * dy2, gy = dx2 * a.dy;
+  const double scale = dx2 * dy2;
+  const double c_field = a.field ? a.amp * (*a.fmax) : 0.0;
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, fd), i = k - j * nx;
+    double f = f_point(a.eps, a.X, a.Y, a.xi[i], a.yj[j], a.ai[i], a.exi[i], a.eyj[j], a.ebj[j]);
+    if (a.field) f = f + c_field * a.field[k];
+    const double ai = a.ai[i], bj = a.bj[j];
+    double s, w, c, e, n;
+    if (a.scheme == 0) {
+      w = cx - ai * gx;
+      e = cx;
+      s = cy - bj * gy;
+      n = cy;
+      c = (ai * gx + bj * gy) - 2.0 * (cx + cy);
+    } else {
+      w = cx - 0.5 * (ai * gx);
+      e = cx + 0.5 * (ai * gx);
+      s = cy - 0.5 * (bj * gy);
+      n = cy + 0.5 * (bj * gy);
+      c = -2.0 * (cx + cy);
+    }
+    double r = scale * f;
+    if (j == 0) r = r - s * a.uy0[i];
+    if (j == ny - 1) r = (a.bc == 0) ? r - n * a.uyY[i] : r - (n * a.dy) * a.gyY[i];
+    if (i == 0) r = r - w * a.ux0[j];
+    if (i == nx - 1) r = (a.bc == 0) ? r - e * a.uxX[j] : r - (e * a.dx) * a.gxX[j];
+    if (a.bc == 1) {
+      if (i == nx - 1) c = c + e;
+      if (j == ny - 1) c = c + n;
+    }
+    a.S[k] = (j == 0) ? 0.0 : s;
+    a.W[k] = (i == 0) ? 0.0 : w;
+    a.C[k] = c;
+    a.E[k] = (i == nx - 1) ? 0.0 : e;
+    a.N[k] = (j == ny - 1) ? 0.0 : n;
+    a.rhs[k] = r;
+  }
+}
+
+hipError_t launch_assemble(const AssembleArgs &a, const Stream1D &g, hipStream_t s) {
+  FastDiv fd;
+  // (host computes fd in the same way as adr_capi.cpp::make_fastdiv)
+  {
+    uint32_t d = (uint32_t)a.nx, sh = 0;
+    while ((1ull << sh) < d) ++sh;
+    fd.d = d;
+    fd.s = sh;
+    fd.m = (uint32_t)(((((uint64_t)1) << 32) * ((((uint64_t)1) << sh) - d)) / d + 1);
+  }
+  if (a.field) {
+    hipLaunchKernelGGL(k_fmax, dim3(g.nblk), dim3(BLK), 0, s, a, g, fd);
+    hipLaunchKernelGGL(k_fmax_fin, dim3(1), dim3(BLK), 0, s, a, g);
+  }
+  hipLaunchKernelGGL(k_assemble, dim3(g.nblk), dim3(BLK), 0, s, a, g, fd);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// SpMV and inner products.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLK) void k_spmv(Dia A, FastDiv fd, int nx, int ny, const double *__restrict__ x,
+                                              double *__restrict__ v, Stream1D g) {
+  ADR_BLOCK_RANGE(g, beg, end);
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, fd), i = k - j * nx;
+    v[k] = spmv_point(A, x, k, i, j, nx, ny);
+  }
+}
+hipError_t launch_spmv(const Dia &A, FastDiv fd, int nx, int ny, const double *x, double *v,
+                       const Stream1D &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_spmv, dim3(g.nblk), dim3(BLK), 0, s, A, fd, nx, ny, x, v, g);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BLK) void k_dot(const double *__restrict__ x, const double *__restrict__ y,
+                                             Stream1D g, double2 *partials) {
+  ADR_BLOCK_RANGE(g, beg, end);
+  dd acc[1] = {dd{0.0, 0.0}};
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) acc[0] = dd_add(acc[0], dd_prod(x[k], y[k]));
+  block_partials<1, false>(acc, 0.0, partials, g.nblk, blockIdx.x);
+}
+__global__ __launch_bounds__(BLK) void k_dot_fin(const double2 *partials, int nblk, double *out) {
+  const dd r = combine_dd(partials, nblk);
+  if (threadIdx.x == 0) *out = r.hi;
+}
+hipError_t launch_dot(const double *x, const double *y, const Stream1D &g, double2 *partials,
+                      double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(g.nblk), dim3(BLK), 0, s, x, y, g, partials);
+  hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(BLK), 0, s, partials, g.nblk, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB (Section 5.2): vector kernels and their finalize steps.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
+
+// r = b - A x, r^ = r; partials: b.b (A), r.r (B), max|r|.
+__global__ __launch_bounds__(BLK) void k_init(IterBufs B, Stream1D g) {
+  ADR_BLOCK_RANGE(g, beg, end);
+  dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+  double mx = 0.0;
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, B.fd), i = k - j * B.nx;
+    const double bk = B.b[k];
+    const double rk = bk - spmv_point(B.A, B.x, k, i, j, B.nx, B.ny);
+    B.r[k] = rk;
+    B.rh[k] = rk;
+    acc[0] = dd_add(acc[0], dd_prod(bk, bk));
+    acc[1] = dd_add(acc[1], dd_prod(rk, rk));
+    mx = nanmax(mx, fabs(rk));
+  }
+  block_partials<2, true>(acc, mx, B.partials, g.nblk, blockIdx.x);
+}
+__global__ __launch_bounds__(BLK) void k_init_fin(IterBufs B, Stream1D g) {
+  const dd bb = combine_dd(B.partials, g.nblk);
+  const dd rr = combine_dd(B.partials + (size_t)g.nblk, g.nblk);
+  const double rmax = combine_max(B.partials + (size_t)3 * g.nblk, g.nblk);
+  if (threadIdx.x != 0) return;
+  SolveState &S = *B.st;
+  S.maxit = B.maxit;
+  S.iter = 0;
+  S.hist_len = 0;
+  S.half_step = 0;
+  S.zero_x = 0;
+  S.rho = S.rho_prev = S.alpha = S.omega = S.beta = 0.0;
+  const double bnorm = sqrt(bb.hi);
+  S.bnorm = bnorm;
+  if (bnorm == 0.0) {
+    B.hist_l2[0] = 0.0;
+    B.hist_max[0] = 0.0;
+    S.hist_len = 1;
+    S.zero_x = 1;
+    S.status = 0;
+    S.phase = DONE;
+    return;
+  }
+  S.thr = B.tol * bnorm;
+  const double rnorm = sqrt(rr.hi);
+  B.hist_l2[0] = rnorm;
+  B.hist_max[0] = rmax;
+  S.hist_len = 1;
+  if (!finite(rnorm)) { S.status = 5; S.phase = DONE; return; }
+  if (rnorm < S.thr) { S.status = 0; S.phase = DONE; return; }
+  S.rho = rr.hi;  // r^ = r, so r^.r is the same double-double sum
+  if (B.maxit < 1) { S.status = 1; S.phase = DONE; return; }
+  S.iter = 1;
+  if (!finite(S.rho)) { S.status = 5; S.phase = DONE; return; }
+  if (S.rho == 0.0) { S.status = 2; S.phase = DONE; return; }
+  S.status = 1;
+  S.phase = RUNNING;
+}
+__global__ __launch_bounds__(BLK) void k_zero_x(IterBufs B, Stream1D g) {
+  if (!B.st->zero_x) return;
+  ADR_BLOCK_RANGE(g, beg, end);
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) B.x[k] = 0.0;
+}
+hipError_t launch_init(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_init_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_zero_x, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  return hipGetLastError();
+}
+
+// p = r (first pass) or p = fma(beta, fma(-omega, v, p), r).
+__global__ __launch_bounds__(BLK) void k_pass_p(IterBufs B, Stream1D g) {
+  if (B.st->phase != RUNNING) return;
+  ADR_BLOCK_RANGE(g, beg, end);
+  if (B.st->iter == 1) {
+    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) B.p[k] = B.r[k];
+  } else {
+    const double beta = B.st->beta, omega = B.st->omega;
+    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) B.p[k] = fma(beta, fma(-omega, B.v[k], B.p[k]), B.r[k]);
+  }
+}
+hipError_t launch_pass_p(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_p, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  return hipGetLastError();
+}
+
+// v = A p^; partial r^.v; finalize alpha = rho / (r^.v).
+__global__ __launch_bounds__(BLK) void k_pass_v(IterBufs B, Stream1D g) {
+  if (B.st->phase != RUNNING) return;
+  ADR_BLOCK_RANGE(g, beg, end);
+  dd acc[1] = {dd{0.0, 0.0}};
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, B.fd), i = k - j * B.nx;
+    const double vk = spmv_point(B.A, B.ph, k, i, j, B.nx, B.ny);
+    B.v[k] = vk;
+    acc[0] = dd_add(acc[0], dd_prod(B.rh[k], vk));
+  }
+  block_partials<1, false>(acc, 0.0, B.partials, g.nblk, blockIdx.x);
+}
+__global__ __launch_bounds__(BLK) void k_pass_v_fin(IterBufs B, Stream1D g) {
+  if (B.st->phase != RUNNING) return;
+  const dd rv = combine_dd(B.partials, g.nblk);
+  if (threadIdx.x != 0) return;
+  SolveState &S = *B.st;
+  S.alpha = S.rho / rv.hi;
+  if (!finite(S.alpha)) { S.status = 5; S.phase = DONE; }
+}
+hipError_t launch_pass_v(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_v, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_pass_v_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  return hipGetLastError();
+}
+
+// s = r - alpha v; partials s.s, max|s|; finalize the half-step test.
+__global__ __launch_bounds__(BLK) void k_pass_s(IterBufs B, Stream1D g) {
+  if (B.st->phase != RUNNING) return;
+  ADR_BLOCK_RANGE(g, beg, end);
+  const double alpha = B.st->alpha;
+  dd acc[1] = {dd{0.0, 0.0}};
+  double mx = 0.0;
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const double sk = fma(-alpha, B.v[k], B.r[k]);
+    B.s[k] = sk;
+    acc[0] = dd_add(acc[0], dd_prod(sk, sk));
+    mx = nanmax(mx, fabs(sk));
+  }
+  block_partials<1, true>(acc, mx, B.partials, g.nblk, blockIdx.x);
+}
+__global__ __launch_bounds__(BLK) void k_pass_s_fin(IterBufs B, Stream1D g) {
+  if (B.st->phase != RUNNING) return;
+  const dd ss = combine_dd(B.partials, g.nblk);
+  const double smax = combine_max(B.partials + (size_t)3 * g.nblk, g.nblk);
+  if (threadIdx.x != 0) return;
+  SolveState &S = *B.st;
+  const double snorm = sqrt(ss.hi);
+  if (!finite(snorm)) { S.status = 5; S.phase = DONE; return; }
+  if (snorm < S.thr) {
+    B.hist_l2[S.iter] = snorm;
+    B.hist_max[S.iter] = smax;
+    S.hist_len = S.iter + 1;
+    S.half_step = 1;
+    S.status = 0;
+    S.phase = HALF_STEP;  // x += alpha p^ is left to the x/r kernel
+  }
+}
+hipError_t launch_pass_s(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_s, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_pass_s_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  return hipGetLastError();
+}
+
+// t = A z; partials t.s, t.t; finalize omega = (t.s)/(t.t).
+__global__ __launch_bounds__(BLK) void k_pass_t(IterBufs B, Stream1D g) {
+  if (B.st->phase != RUNNING) return;
+  ADR_BLOCK_RANGE(g, beg, end);
+  dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, B.fd), i = k - j * B.nx;
+    const double tk = spmv_point(B.A, B.z, k, i, j, B.nx, B.ny);
+    B.t[k] = tk;
+    acc[0] = dd_add(acc[0], dd_prod(tk, B.s[k]));
+    acc[1] = dd_add(acc[1], dd_prod(tk, tk));
+  }
+  block_partials<2, false>(acc, 0.0, B.partials, g.nblk, blockIdx.x);
+}
+__global__ __launch_bounds__(BLK) void k_pass_t_fin(IterBufs B, Stream1D g) {
+  if (B.st->phase != RUNNING) return;
+  const dd ts = combine_dd(B.partials, g.nblk);
+  const dd tt = combine_dd(B.partials + (size_t)g.nblk, g.nblk);
+  if (threadIdx.x != 0) return;
+  SolveState &S = *B.st;
+  S.omega = ts.hi / tt.hi;
+  if (!finite(S.omega)) { S.status = 5; S.phase = DONE; }
+}
+hipError_t launch_pass_t(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_t, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_pass_t_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  return hipGetLastError();
+}
+
+// x = fma(omega, z, fma(alpha, p^, x)); r = fma(-omega, t, s); partials
+// r.r, r^.r, max|r|; finalize: history, stopping tests, next beta.
+// After a half-step exit: x = fma(alpha, p^, x) only.
+__global__ __launch_bounds__(BLK) void k_pass_xr(IterBufs B, Stream1D g) {
+  const int phase = B.st->phase;
+  if (phase == DONE) return;
+  ADR_BLOCK_RANGE(g, beg, end);
+  const double alpha = B.st->alpha;
+  if (phase == HALF_STEP) {
+    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) B.x[k] = fma(alpha, B.ph[k], B.x[k]);
+    return;
+  }
+  const double omega = B.st->omega;
+  dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
+  double mx = 0.0;
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    B.x[k] = fma(omega, B.z[k], fma(alpha, B.ph[k], B.x[k]));
+    const double rk = fma(-omega, B.t[k], B.s[k]);
+    B.r[k] = rk;
+    acc[0] = dd_add(acc[0], dd_prod(rk, rk));
+    acc[1] = dd_add(acc[1], dd_prod(B.rh[k], rk));
+    mx = nanmax(mx, fabs(rk));
+  }
+  block_partials<2, true>(acc, mx, B.partials, g.nblk, blockIdx.x);
+}
+__global__ __launch_bounds__(BLK) void k_pass_xr_fin(IterBufs B, Stream1D g) {
+  const int phase = B.st->phase;
+  if (phase == DONE) return;
+  if (phase == HALF_STEP) {
+    if (threadIdx.x == 0) B.st->phase = DONE;
+    return;
+  }
+  const dd rr = combine_dd(B.partials, g.nblk);
+  const dd rhr = combine_dd(B.partials + (size_t)g.nblk, g.nblk);
+  const double rmax = combine_max(B.partials + (size_t)3 * g.nblk, g.nblk);
+  if (threadIdx.x != 0) return;
+  SolveState &S = *B.st;
+  const int i = S.iter;
+  const double rnorm = sqrt(rr.hi);
+  B.hist_l2[i] = rnorm;
+  B.hist_max[i] = rmax;
+  S.hist_len = i + 1;
+  S.rho_prev = S.rho;
+  S.rho = rhr.hi;
+  if (!finite(rnorm)) { S.status = 5; S.phase = DONE; return; }
+  if (rnorm < S.thr) { S.status = 0; S.phase = DONE; return; }
+  if (S.omega == 0.0) { S.status = 3; S.phase = DONE; return; }
+  if (i >= S.maxit) { S.status = 1; S.phase = DONE; return; }
+  S.iter = i + 1;
+  if (!finite(S.rho)) { S.status = 5; S.phase = DONE; return; }
+  if (S.rho == 0.0) { S.status = 2; S.phase = DONE; return; }
+  S.beta = (S.rho / S.rho_prev) * (S.alpha / S.omega);
+}
+hipError_t launch_pass_xr(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_xr, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_pass_xr_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  return hipGetLastError();
+}
+
+// ||b - A x||_2 (double-double), written to *out.
+__global__ __launch_bounds__(BLK) void k_true_res(IterBufs B, Stream1D g) {
+  ADR_BLOCK_RANGE(g, beg, end);
+  dd acc[1] = {dd{0.0, 0.0}};
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, B.fd), i = k - j * B.nx;
+    const double e = B.b[k] - spmv_point(B.A, B.x, k, i, j, B.nx, B.ny);
+    acc[0] = dd_add(acc[0], dd_prod(e, e));
+  }
+  block_partials<1, false>(acc, 0.0, B.partials, g.nblk, blockIdx.x);
+}
+hipError_t launch_true_residual(const IterBufs &B, const Stream1D &g, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_true_res, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(BLK), 0, s, B.partials, g.nblk, out);
+  return hipGetLastError();
+}
+
+}  // namespace adr

@@ -1,0 +1,459 @@
+// Anti-diagonal wavefront kernels for gfx950: the ILU(0) factorisation of
+// the five-point matrix and the forward (L) / backward (U) triangular sweeps
+// that apply M^{-1} = U^{-1} L^{-1} (Section 5.1 of the paper).
+//
+// Every point of these recurrences depends on its predecessor in x and in y,
+// so the points of one anti-diagonal (i + j = const) are independent.  The
+// grid is cut into strips of R rows; one wave owns a strip and walks it
+// column by column with a skew of one column per row (wave lane l handles
+// strip row l-1 and, at step tau, sweep column tau - l), so at every step
+// the wave holds R consecutive points of one anti-diagonal:
+//   * the x-predecessor is the lane's own result of the previous step;
+//   * the y-predecessor is the result of lane l-1 at the previous step,
+//     moved one lane up with a DPP wave shift (no LDS, no barrier);
+//   * lane 0 is a "ghost" row: it replays the last row of the strip below
+//     (published by that strip's wave through a hand-off buffer in global
+//     memory, one relaxed agent-scope atomic per value, with a sentinel
+//     meaning "not yet written"), with coefficients chosen so that its
+//     result is exactly the published value.
+// Coefficients and right-hand sides are brought in by coalesced loads of
+// skewed R x W tiles into registers two chunks ahead, transposed through LDS,
+// and the results leave the same way.  Strips start in ticket order, so a
+// wave only ever waits for a wave that is already running.
+// The per-point formulas are the fixed fma orders of include/adr.h; the
+// wavefront order does not change a single rounding.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "adr_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace adr {
+
+namespace {
+
+constexpr unsigned SPIN_LIMIT = 1u << 20;   // polls before a wait is declared failed
+
+__device__ __forceinline__ double dpp_up(double v) {
+  // lane l receives lane l-1's value; lane 0 receives 0
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x138, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ float dpp_up(float v) {
+  const int r = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true);
+  return __int_as_float(r);
+}
+
+__device__ __forceinline__ void handoff_put(uint64_t *p, double v) {
+  uint64_t b = (uint64_t)__double_as_longlong(v);
+  if (b == HANDOFF_EMPTY) b = CANON_NAN;
+  __hip_atomic_store(p, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t handoff_get(const uint64_t *p) {
+  return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until this lane's hand-off value (if `need`) is written; returns it
+// and marks the slot empty again for the next launch.  A wait that exceeds
+// SPIN_LIMIT polls reports through *err and marks the wave `dead`, after
+// which it no longer waits (the results are then invalid, but every wave
+// still runs to its end).
+__device__ __forceinline__ double handoff_take(const uint64_t *p, bool need, uint64_t prefetched, int *err,
+                                               bool &dead) {
+  uint64_t b = need ? prefetched : 0;
+  unsigned spins = 0;
+  while (!dead && __builtin_amdgcn_ballot_w64(need && b == HANDOFF_EMPTY) != 0ull) {
+    if (need && b == HANDOFF_EMPTY) b = handoff_get(p);
+    if (++spins > SPIN_LIMIT) {
+      dead = true;
+      if (threadIdx.x == 0) atomicOr(err, 1);
+    } else {
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  if (need && b == HANDOFF_EMPTY) b = 0;
+  if (need) __hip_atomic_store(const_cast<uint64_t *>(p), HANDOFF_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return need ? __longlong_as_double((long long)b) : 0.0;
+}
+
+__device__ __forceinline__ void strip_finish(const SweepSync &sy, int nstrips) {
+  if (threadIdx.x == 0) {
+    const unsigned fin = atomicAdd(&sy.ticket[1], 1u);
+    if (fin == (unsigned)nstrips - 1) {
+      // every strip has taken its ticket and finished: reset for the next launch
+      __hip_atomic_store(&sy.ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&sy.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// L / U sweeps.
+//   OP 0 (L): y = fma(-ls, y_s, fma(-lw, y_w, q))          inputs q, lw, ls
+//   OP 1 (U): z = fma(-N, z_n, fma(-E, z_e, y)) * invd     inputs y, E, N, invd
+// PREC 0: factors FP64; 1: factors FP32, arithmetic FP64; 2: arithmetic FP32.
+// ---------------------------------------------------------------------------
+struct SweepParams {
+  int nx, ny, nstrips;
+  const double *v;      // q (L) or y (U)
+  const void *f1, *f2, *f3;   // lw, ls (L) or E, N, invd (U); double or float per PREC
+  double *out;
+  SweepSync sync;
+  const int32_t *phase;
+};
+
+template <int R, int W, int OP, int PREC>
+__global__ __launch_bounds__(64) void k_sweep(SweepParams p) {
+  using TF = typename std::conditional<PREC == 0, double, float>::type;
+  using CT = typename std::conditional<PREC == 2, float, double>::type;
+  constexpr int L = R + 1;             // lanes in use (lane 0 = ghost row)
+  constexpr int RPP = 64 / W;          // tile rows per load pass
+  constexpr int NP = (L + RPP - 1) / RPP;
+  constexpr int NIN = (OP == 0) ? 3 : 4;
+  static_assert(L <= 64, "strip too tall");
+  __shared__ CT s_in[NIN][L][W + 1];
+  __shared__ double s_out[L][W + 1];
+
+  if (p.phase && *p.phase != RUNNING) return;
+  const int lane = threadIdx.x;
+  unsigned tk = 0;
+  if (lane == 0) tk = atomicAdd(&p.sync.ticket[0], 1u);
+  const int strip = __builtin_amdgcn_readfirstlane((int)tk);
+  const int nx = p.nx, ny = p.ny;
+  const int base = strip * R;
+  const int rows = min(R, ny - base);
+  const bool has_prev = strip > 0, has_next = base + R < ny;
+  const uint64_t *ho_in = p.sync.handoff + (size_t)(has_prev ? strip - 1 : 0) * nx;
+  uint64_t *ho_out = p.sync.handoff + (size_t)strip * nx;
+  const int nsteps = nx + rows;
+  const int nchunks = (nsteps + W - 1) / W;
+  const int lrow = lane / W, lcol = lane % W;
+  bool dead = false;
+  const TF *f1 = (const TF *)p.f1, *f2 = (const TF *)p.f2, *f3 = (const TF *)p.f3;
+
+  // tile row l (>= 1) -> grid row; sweep column offset -> grid column
+  auto grow = [&](int l) { return OP == 0 ? base + l - 1 : ny - base - l; };
+  auto gcol = [&](int co) { return OP == 0 ? co : nx - 1 - co; };
+
+  CT stg0[NIN][NP], stg1[NIN][NP];
+  auto issue = [&](CT (&b)[NIN][NP], int c) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int l = q * RPP + lrow;
+      const int co = c * W + lcol - l;   // lane l handles sweep column tau - l
+      const bool ok = (l >= 1) && (l <= rows) && (co >= 0) && (co < nx);
+      const size_t k = ok ? (size_t)grow(l) * nx + gcol(co) : 0;
+      b[0][q] = ok ? (CT)p.v[k] : (CT)0;
+      b[1][q] = ok ? (CT)f1[k] : (CT)0;
+      b[2][q] = ok ? (CT)f2[k] : (CT)0;
+      if (NIN == 4) b[NIN - 1][q] = ok ? (CT)f3[k] : (CT)0;
+    }
+  };
+  // ghost row (tile row 0) for chunk c: last row of the previous strip at
+  // sweep columns c*W + lcol (lanes with lrow == 0)
+  auto ghost_need = [&](int c) {
+    const int co = c * W + lcol;
+    return has_prev && lrow == 0 && co < nx;
+  };
+  auto ghost_prefetch = [&](int c) -> uint64_t {
+    return ghost_need(c) ? handoff_get(ho_in + gcol(c * W + lcol)) : 0ull;
+  };
+  auto to_lds = [&](CT (&b)[NIN][NP], int c, uint64_t gpre) {
+    const bool need = ghost_need(c);
+    const double gv = handoff_take(ho_in + (need ? gcol(c * W + lcol) : 0), need, gpre, p.sync.err, dead);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int l = q * RPP + lrow;
+      if (l < L) {
+#pragma unroll
+        for (int m = 0; m < NIN; ++m) s_in[m][l][lcol] = b[m][q];
+      }
+    }
+    if (lrow == 0) {
+      s_in[0][0][lcol] = (CT)gv;
+      if (OP == 1) s_in[3][0][lcol] = (CT)1;
+    }
+  };
+
+  CT west = (CT)0;
+  auto compute = [&](int c) {
+    const int lr = lane < L ? lane : L - 1;
+    const int pub_lane = has_next ? rows : -1;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const CT a0 = s_in[0][lr][w], a1 = s_in[1][lr][w], a2 = s_in[2][lr][w];
+      const CT south = dpp_up(west);
+      CT v = fma(-a2, south, fma(-a1, west, a0));
+      if (OP == 1) v = v * s_in[NIN - 1][lr][w];
+      if (lane < L) s_out[lane][w] = (double)v;
+      west = v;
+      if (lane == pub_lane) {
+        const int co = c * W + w - rows;
+        if (co >= 0 && co < nx) handoff_put(ho_out + gcol(co), (double)v);
+      }
+    }
+  };
+  auto store = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int l = q * RPP + lrow;
+      const int co = c * W + lcol - l;
+      const bool ok = (l >= 1) && (l <= rows) && (co >= 0) && (co < nx);
+      if (ok) p.out[(size_t)grow(l) * nx + gcol(co)] = s_out[l][lcol];
+    }
+  };
+
+  issue(stg0, 0);
+  if (nchunks > 1) issue(stg1, 1);
+  uint64_t g0 = ghost_prefetch(0), g1 = 0;
+  for (int c = 0; c < nchunks; c += 2) {
+    to_lds(stg0, c, g0);
+    if (c + 1 < nchunks) g1 = ghost_prefetch(c + 1);
+    if (c + 2 < nchunks) issue(stg0, c + 2);
+    __syncthreads();
+    compute(c);
+    __syncthreads();
+    store(c);
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      to_lds(stg1, c + 1, g1);
+      if (c + 2 < nchunks) g0 = ghost_prefetch(c + 2);
+      if (c + 3 < nchunks) issue(stg1, c + 3);
+      __syncthreads();
+      compute(c + 1);
+      __syncthreads();
+      store(c + 1);
+      __syncthreads();
+    }
+  }
+  strip_finish(p.sync, p.nstrips);
+}
+
+// ---------------------------------------------------------------------------
+// ILU(0) factorisation sweep (forward, like L).  Per point:
+//   lw = W * invd_w,  ls = S * invd_s,  d = fma(-ls, N_s, fma(-lw, E_w, C)),
+//   invd = 1 / d  (0 and a recorded bad index if d is 0 or not finite).
+// Carried: invd and E of the x-predecessor (own lane); invd and N of the
+// y-predecessor (lane below, DPP).  The ghost lane replays the last row of
+// the strip below: its invd from the hand-off buffer, its N from A.
+// ---------------------------------------------------------------------------
+struct FactorParams {
+  int nx, ny, nstrips;
+  Dia A;
+  Factors64 f;
+  Factors32 h;   // optional FP32 copies (null pointers: not written)
+  SweepSync sync;
+  unsigned long long *bad;   // min over bad pivot indices (pre-set to ~0)
+};
+
+template <int R, int W>
+__global__ __launch_bounds__(64) void k_ilu0(FactorParams p) {
+  constexpr int L = R + 1, RPP = 64 / W, NP = (L + RPP - 1) / RPP, NIN = 5, NOUT = 3;
+  __shared__ double s_in[NIN][L][W + 1];
+  __shared__ double s_out[NOUT][L][W + 1];
+  const int lane = threadIdx.x;
+  unsigned tk = 0;
+  if (lane == 0) tk = atomicAdd(&p.sync.ticket[0], 1u);
+  const int strip = __builtin_amdgcn_readfirstlane((int)tk);
+  const int nx = p.nx, ny = p.ny;
+  const int base = strip * R;
+  const int rows = min(R, ny - base);
+  const bool has_prev = strip > 0, has_next = base + R < ny;
+  const uint64_t *ho_in = p.sync.handoff + (size_t)(has_prev ? strip - 1 : 0) * nx;
+  uint64_t *ho_out = p.sync.handoff + (size_t)strip * nx;
+  const int nsteps = nx + rows;
+  const int nchunks = (nsteps + W - 1) / W;
+  const int lrow = lane / W, lcol = lane % W;
+  bool dead = false;
+  const double *in[NIN] = {p.A.S, p.A.W, p.A.C, p.A.E, p.A.N};
+
+  double stg[NIN][NP];
+  auto issue = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int l = q * RPP + lrow;
+      const int co = c * W + lcol - l;
+      const int row = base + l - 1;
+      const bool inr = (co >= 0) && (co < nx);
+      const bool ok = (l >= 1) && (l <= rows) && inr;
+      const bool ghostN = (l == 0) && has_prev && inr;   // N of the row below the strip
+      const size_t k = (ok || ghostN) ? (size_t)row * nx + co : 0;
+#pragma unroll
+      for (int m = 0; m < NIN; ++m) stg[m][q] = ok ? in[m][k] : 0.0;
+      if (ghostN) stg[4][q] = in[4][k];
+    }
+  };
+  auto to_lds = [&](int c) {
+    const int co = c * W + lcol;
+    const bool need = has_prev && lrow == 0 && co < nx;
+    uint64_t pre = need ? handoff_get(ho_in + co) : 0ull;
+    const double gv = handoff_take(ho_in + (need ? co : 0), need, pre, p.sync.err, dead);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int l = q * RPP + lrow;
+      if (l < L) {
+#pragma unroll
+        for (int m = 0; m < NIN; ++m) s_in[m][l][lcol] = stg[m][q];
+      }
+    }
+    if (lrow == 0) s_in[2][0][lcol] = gv;   // ghost: C slot carries the hand-off invd
+  };
+
+  double invd_w = 0.0, e_w = 0.0, n_prev = 0.0;
+  const int lr = lane < L ? lane : L - 1;
+  for (int c = 0; c < nchunks; ++c) {
+    issue(c);
+    to_lds(c);
+    __syncthreads();
+    for (int w = 0; w < W; ++w) {
+      const double S = s_in[0][lr][w], Wc = s_in[1][lr][w], C = s_in[2][lr][w];
+      const double E = s_in[3][lr][w], N = s_in[4][lr][w];
+      const double invd_s = dpp_up(invd_w);
+      const double n_s = dpp_up(n_prev);
+      const double lw = Wc * invd_w;
+      const double ls = S * invd_s;
+      double d = fma(-lw, e_w, C);
+      d = fma(-ls, n_s, d);
+      const int co = c * W + w - lane;
+      const bool valid = lane >= 1 && lane <= rows && co >= 0 && co < nx;
+      const bool bad = valid && (d == 0.0 || !isfinite(d));
+      double invd = (valid && !bad) ? 1.0 / d : 0.0;
+      if (lane == 0) invd = C;
+      if (bad) atomicMin(p.bad, (unsigned long long)((size_t)(base + lane - 1) * nx + co));
+      if (lane < L) {
+        s_out[0][lane][w] = lw;
+        s_out[1][lane][w] = ls;
+        s_out[2][lane][w] = invd;
+      }
+      if (has_next && lane == rows && valid) handoff_put(ho_out + co, invd);
+      invd_w = invd;
+      e_w = E;
+      n_prev = N;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int l = q * RPP + lrow;
+      const int co = c * W + lcol - l;
+      const bool ok = (l >= 1) && (l <= rows) && (co >= 0) && (co < nx);
+      if (ok) {
+        const size_t k = (size_t)(base + l - 1) * nx + co;
+        p.f.lw[k] = s_out[0][l][lcol];
+        p.f.ls[k] = s_out[1][l][lcol];
+        p.f.invd[k] = s_out[2][l][lcol];
+        if (p.h.lw) {
+          p.h.lw[k] = (float)s_out[0][l][lcol];
+          p.h.ls[k] = (float)s_out[1][l][lcol];
+          p.h.invd[k] = (float)s_out[2][l][lcol];
+          p.h.E[k] = (float)p.A.E[k];
+          p.h.N[k] = (float)p.A.N[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  strip_finish(p.sync, p.nstrips);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+static int strips_of(int ny, int rows) { return (ny + rows - 1) / rows; }
+
+hipError_t launch_ilu0(const Dia &A, int nx, int ny, int rows, Factors64 f64, Factors32 f32,
+                       const SweepSync &sync, int64_t *bad, hipStream_t s) {
+  FactorParams p;
+  p.nx = nx;
+  p.ny = ny;
+  p.A = A;
+  p.f = f64;
+  p.h = f32;
+  p.sync = sync;
+  p.bad = (unsigned long long *)bad;
+  switch (rows) {
+    case 15:
+      p.nstrips = strips_of(ny, 15);
+      hipLaunchKernelGGL((k_ilu0<15, 32>), dim3(p.nstrips), dim3(64), 0, s, p);
+      break;
+    case 31:
+      p.nstrips = strips_of(ny, 31);
+      hipLaunchKernelGGL((k_ilu0<31, 32>), dim3(p.nstrips), dim3(64), 0, s, p);
+      break;
+    case 63:
+      p.nstrips = strips_of(ny, 63);
+      hipLaunchKernelGGL((k_ilu0<63, 16>), dim3(p.nstrips), dim3(64), 0, s, p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int OP, int PREC>
+static hipError_t launch_sweep_t(int nx, int ny, int rows, SweepParams p, hipStream_t s) {
+  p.nx = nx;
+  p.ny = ny;
+  switch (rows) {
+    case 15:
+      p.nstrips = strips_of(ny, 15);
+      hipLaunchKernelGGL((k_sweep<15, 32, OP, PREC>), dim3(p.nstrips), dim3(64), 0, s, p);
+      break;
+    case 31:
+      p.nstrips = strips_of(ny, 31);
+      hipLaunchKernelGGL((k_sweep<31, 32, OP, PREC>), dim3(p.nstrips), dim3(64), 0, s, p);
+      break;
+    case 63:
+      p.nstrips = strips_of(ny, 63);
+      hipLaunchKernelGGL((k_sweep<63, 16, OP, PREC>), dim3(p.nstrips), dim3(64), 0, s, p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lsweep(int nx, int ny, int rows, int precision, const Factors64 &f64,
+                         const Factors32 &f32, const double *q, double *y, const SweepSync &sync,
+                         const int32_t *phase, hipStream_t s) {
+  SweepParams p{};
+  p.v = q;
+  p.out = y;
+  p.sync = sync;
+  p.phase = phase;
+  if (precision == 0) {
+    p.f1 = f64.lw;
+    p.f2 = f64.ls;
+    return launch_sweep_t<0, 0>(nx, ny, rows, p, s);
+  }
+  p.f1 = f32.lw;
+  p.f2 = f32.ls;
+  return precision == 1 ? launch_sweep_t<0, 1>(nx, ny, rows, p, s) : launch_sweep_t<0, 2>(nx, ny, rows, p, s);
+}
+
+hipError_t launch_usweep(int nx, int ny, int rows, int precision, const Dia &A,
+                         const Factors64 &f64, const Factors32 &f32, const double *y, double *z,
+                         const SweepSync &sync, const int32_t *phase, hipStream_t s) {
+  SweepParams p{};
+  p.v = y;
+  p.out = z;
+  p.sync = sync;
+  p.phase = phase;
+  if (precision == 0) {
+    p.f1 = A.E;
+    p.f2 = A.N;
+    p.f3 = f64.invd;
+    return launch_sweep_t<1, 0>(nx, ny, rows, p, s);
+  }
+  p.f1 = f32.E;
+  p.f2 = f32.N;
+  p.f3 = f32.invd;
+  return precision == 1 ? launch_sweep_t<1, 1>(nx, ny, rows, p, s) : launch_sweep_t<1, 2>(nx, ny, rows, p, s);
+}
+
+}  // namespace adr
