@@ -184,6 +184,11 @@ adr_status adr_spmv(adr_problem *p, const double *x_dev, double *v_dev);
  *   z_k = fma(-N, z_{k+nx}, fma(-E, z_{k+1}, y_k)) * invd_k. */
 adr_status adr_precond(adr_problem *p, const double *q_dev, double *z_dev);
 
+/* The two halves of adr_precond, one wavefront kernel each:
+ * adr_lsolve: y = L^{-1} q;  adr_usolve: z = U^{-1} y  (device vectors). */
+adr_status adr_lsolve(adr_problem *p, const double *q_dev, double *y_dev);
+adr_status adr_usolve(adr_problem *p, const double *y_dev, double *z_dev);
+
 /* Double-double inner product of two device vectors of length n, rounded to
  * FP64, written to *out (host). */
 adr_status adr_dot(const double *x_dev, const double *y_dev, int64_t n, void *stream,
@@ -192,8 +197,8 @@ adr_status adr_dot(const double *x_dev, const double *y_dev, int64_t n, void *st
 /* Bytes of device memory the problem holds (after ilu0 / solve buffers). */
 size_t adr_device_bytes(const adr_problem *p);
 
-/* Sweep geometry in use: rows per strip (R) for the wavefront kernels, or 0
- * to pick automatically.  For tuning and tests. */
+/* Sweep geometry: rows per strip (R = 15 or 31) for the wavefront kernels,
+ * or 0 to pick automatically.  For tuning and tests. */
 adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
 
 const char *adr_status_str(int32_t status);

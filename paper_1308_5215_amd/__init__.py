@@ -149,6 +149,18 @@ class Problem:
         _lib.check(_lib.load().adr_precond(self._h, _dev_f64(q, self.n, "q"), _dev_f64(z, self.n, "out")))
         return z
 
+    def lsolve(self, q, out=None):
+        torch = _torch()
+        y = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _lib.check(_lib.load().adr_lsolve(self._h, _dev_f64(q, self.n, "q"), _dev_f64(y, self.n, "out")))
+        return y
+
+    def usolve(self, y, out=None):
+        torch = _torch()
+        z = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _lib.check(_lib.load().adr_usolve(self._h, _dev_f64(y, self.n, "y"), _dev_f64(z, self.n, "out")))
+        return z
+
     def set_sweep_rows(self, rows):
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
 

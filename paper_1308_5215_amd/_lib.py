@@ -17,7 +17,7 @@ FP64, FP32_FACTORS, FP32_SWEEPS = 0, 1, 2
 
 EXPORTS = [
     "adr_assemble", "adr_ilu0", "adr_bicgstab_solve", "adr_destroy", "adr_get_dia", "adr_set_dia",
-    "adr_get_factors", "adr_spmv", "adr_precond", "adr_dot", "adr_device_bytes",
+    "adr_get_factors", "adr_spmv", "adr_precond", "adr_lsolve", "adr_usolve", "adr_dot", "adr_device_bytes",
     "adr_set_sweep_rows", "adr_status_str", "adr_last_error",
 ]
 
@@ -61,6 +61,9 @@ def load():
     L.adr_spmv.argtypes = [P, P, P]
     L.adr_precond.restype = ctypes.c_int
     L.adr_precond.argtypes = [P, P, P]
+    for nm in ("adr_lsolve", "adr_usolve"):
+        getattr(L, nm).restype = ctypes.c_int
+        getattr(L, nm).argtypes = [P, P, P]
     L.adr_dot.restype = ctypes.c_int
     L.adr_dot.argtypes = [P, P, i64, P, D]
     L.adr_device_bytes.restype = ctypes.c_size_t

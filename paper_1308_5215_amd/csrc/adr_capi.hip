@@ -81,9 +81,7 @@ void dfree(T *&p) {
 }
 
 int auto_rows(int ny) {
-  if (ny >= 8192) return 63;
-  if (ny >= 2048) return 31;
-  return 15;
+  return ny >= 2048 ? 31 : 15;
 }
 
 }  // namespace
@@ -423,8 +421,8 @@ adr_status adr_get_factors(const adr_problem *P, double *lw, double *ls, double 
 adr_status adr_set_sweep_rows(adr_problem *P, int32_t rows) {
   g_last_error.clear();
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
-  if (rows != 0 && rows != 15 && rows != 31 && rows != 63)
-    return fail(ADR_ERR_ARG, "rows must be 0, 15, 31 or 63 (got %d)", rows);
+  if (rows != 0 && rows != 15 && rows != 31)
+    return fail(ADR_ERR_ARG, "rows must be 0, 15 or 31 (got %d)", rows);
   P->rows = rows;
   return ADR_OK;
 }
@@ -482,6 +480,22 @@ adr_status adr_precond(adr_problem *P, const double *q, double *z) {
   const int rows = P->sweep_rows();
   HIP_TRY(launch_lsweep(P->nx, P->ny, rows, P->precision, f64_of(P), f32_of(P), q, P->y, P->sync(), nullptr, P->stream));
   HIP_TRY(launch_usweep(P->nx, P->ny, rows, P->precision, P->dia(), f64_of(P), f32_of(P), P->y, z, P->sync(), nullptr, P->stream));
+  return check_device_fault(P);
+}
+
+adr_status adr_lsolve(adr_problem *P, const double *q, double *y) {
+  g_last_error.clear();
+  if (!P || !q || !y) return fail(ADR_ERR_ARG, "NULL argument");
+  if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
+  HIP_TRY(launch_lsweep(P->nx, P->ny, P->sweep_rows(), P->precision, f64_of(P), f32_of(P), q, y, P->sync(), nullptr, P->stream));
+  return check_device_fault(P);
+}
+
+adr_status adr_usolve(adr_problem *P, const double *y, double *z) {
+  g_last_error.clear();
+  if (!P || !y || !z) return fail(ADR_ERR_ARG, "NULL argument");
+  if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
+  HIP_TRY(launch_usweep(P->nx, P->ny, P->sweep_rows(), P->precision, P->dia(), f64_of(P), f32_of(P), y, z, P->sync(), nullptr, P->stream));
   return check_device_fault(P);
 }
 

@@ -108,130 +108,218 @@ struct SweepParams {
   const int32_t *phase;
 };
 
-template <int R, int W, int OP, int PREC>
-__global__ __launch_bounds__(64) void k_sweep(SweepParams p) {
+// ---------------------------------------------------------------------------
+// L / U sweeps, warp-specialised.  One workgroup per strip of R rows:
+//   wave 0   compute: walks the strip chunk by chunk (W columns), reading its
+//            inputs from an LDS ring, keeping the chunk's results in
+//            registers, then writing them to an LDS output buffer and
+//            publishing the strip's last row to the hand-off buffer;
+//   wave 1   poller:  waits for the previous strip's published row and puts
+//            it into the ring as tile row 0 (the ghost row);
+//   wave 2   storer:  copies finished output tiles from LDS to global memory;
+//   waves 3+ loaders: each owns every NLD-th chunk: coalesced global loads of
+//            the skewed input tile into registers, then into its ring slot.
+// The waves meet only through LDS flags (workgroup-scope acquire/release):
+// per-slot "loaded" and "ghost" flags, and the compute / store counters.
+// Many loader waves keep many chunks in flight, so the compute wave does not
+// wait on memory latency; it waits only for the previous strip.
+// ---------------------------------------------------------------------------
+namespace {
+
+__device__ __forceinline__ int lds_get(int *c) {
+  return __hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_put(int *c, int v) {
+  __hip_atomic_store(c, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_wait_ge(int *c, int target) {
+  while (lds_get(c) < target) __builtin_amdgcn_s_sleep(1);
+}
+__device__ __forceinline__ void lds_wait_eq(int *c, int target) {
+  while (lds_get(c) != target) __builtin_amdgcn_s_sleep(1);
+}
+
+template <int R, int NIN, int CTB>
+struct SweepShape {
+  static constexpr int W = 16;                      // columns per chunk
+  static constexpr int L = R + 1;                   // tile rows (row 0 = ghost)
+  static constexpr int PITCH = W + 2;               // 16-byte aligned rows
+  static constexpr int NT = (R <= 15) ? 512 : 1024; // threads per workgroup
+  static constexpr int NLD = NT / 64 - 3;           // loader waves
+  static constexpr int LDS_BUDGET = (R <= 15) ? 76 * 1024 : 150 * 1024;   // 2 or 1 workgroups per CU
+  static constexpr int OUT_BYTES = 2 * L * PITCH * 8;
+  static constexpr int CHUNK_BYTES = NIN * L * PITCH * CTB;
+  static constexpr int NC_FIT = (LDS_BUDGET - OUT_BYTES) / CHUNK_BYTES;
+  static constexpr int NC = NC_FIT < 16 ? NC_FIT : 16;   // LDS ring depth (chunks)
+  static_assert(NC >= 4, "LDS ring too small");
+  static constexpr int RPP = 64 / W;                // tile rows per wave pass
+  static constexpr int NP = (L - 1 + RPP - 1) / RPP;   // passes for rows 1..L-1
+};
+
+}  // namespace
+
+template <int R, int OP, int PREC>
+__global__ __launch_bounds__((R <= 15) ? 512 : 1024) void k_sweep_ws(SweepParams p) {
   using TF = typename std::conditional<PREC == 0, double, float>::type;
   using CT = typename std::conditional<PREC == 2, float, double>::type;
-  constexpr int L = R + 1;             // lanes in use (lane 0 = ghost row)
-  constexpr int RPP = 64 / W;          // tile rows per load pass
-  constexpr int NP = (L + RPP - 1) / RPP;
   constexpr int NIN = (OP == 0) ? 3 : 4;
+  using Sh = SweepShape<R, NIN, (int)sizeof(CT)>;
+  constexpr int W = Sh::W, L = Sh::L, PITCH = Sh::PITCH, NC = Sh::NC, NT = Sh::NT, NLD = Sh::NLD;
+  constexpr int RPP = Sh::RPP, NP = Sh::NP;
   static_assert(L <= 64, "strip too tall");
-  __shared__ CT s_in[NIN][L][W + 1];
-  __shared__ double s_out[L][W + 1];
+  __shared__ __align__(16) CT s_in[NC][NIN][L][PITCH];
+  __shared__ __align__(16) double s_out[2][L][PITCH];
+  __shared__ int s_loaded[NC], s_ghost[NC];
+  __shared__ int s_computed, s_stored;
+  __shared__ int s_strip;
 
   if (p.phase && *p.phase != RUNNING) return;
-  const int lane = threadIdx.x;
-  unsigned tk = 0;
-  if (lane == 0) tk = atomicAdd(&p.sync.ticket[0], 1u);
-  const int strip = __builtin_amdgcn_readfirstlane((int)tk);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) {
+    s_strip = (int)atomicAdd(&p.sync.ticket[0], 1u);
+    s_computed = 0;
+    s_stored = 0;
+  }
+  if (tid < NC) {
+    s_loaded[tid] = 0;
+    s_ghost[tid] = 0;
+  }
+  // ghost row of every ring slot: zero values and coefficients (invd = 1)
+  for (int e = tid; e < NC * NIN * PITCH; e += NT) {
+    const int sl = e / (NIN * PITCH), m = (e / PITCH) % NIN, w = e % PITCH;
+    s_in[sl][m][0][w] = (OP == 1 && m == 3) ? (CT)1 : (CT)0;
+  }
+  __syncthreads();
+  const int strip = s_strip;
   const int nx = p.nx, ny = p.ny;
   const int base = strip * R;
   const int rows = min(R, ny - base);
   const bool has_prev = strip > 0, has_next = base + R < ny;
-  const uint64_t *ho_in = p.sync.handoff + (size_t)(has_prev ? strip - 1 : 0) * nx;
-  uint64_t *ho_out = p.sync.handoff + (size_t)strip * nx;
-  const int nsteps = nx + rows;
-  const int nchunks = (nsteps + W - 1) / W;
-  const int lrow = lane / W, lcol = lane % W;
-  bool dead = false;
-  const TF *f1 = (const TF *)p.f1, *f2 = (const TF *)p.f2, *f3 = (const TF *)p.f3;
-
-  // tile row l (>= 1) -> grid row; sweep column offset -> grid column
+  const int nchunks = (nx + rows + W - 1) / W;
+  const int lr = lane / W, lc = lane % W;   // tile (row-in-pass, column) for loads and stores
   auto grow = [&](int l) { return OP == 0 ? base + l - 1 : ny - base - l; };
   auto gcol = [&](int co) { return OP == 0 ? co : nx - 1 - co; };
 
-  CT stg0[NIN][NP], stg1[NIN][NP];
-  auto issue = [&](CT (&b)[NIN][NP], int c) {
+  if (wave >= 3) {
+    // ------------------------------------------------------------ loaders
+    const TF *f1 = (const TF *)p.f1, *f2 = (const TF *)p.f2, *f3 = (const TF *)p.f3;
+    for (int c = wave - 3; c < nchunks; c += NLD) {
+      CT b[NIN][NP];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const int l = q * RPP + lrow;
-      const int co = c * W + lcol - l;   // lane l handles sweep column tau - l
-      const bool ok = (l >= 1) && (l <= rows) && (co >= 0) && (co < nx);
-      const size_t k = ok ? (size_t)grow(l) * nx + gcol(co) : 0;
-      b[0][q] = ok ? (CT)p.v[k] : (CT)0;
-      b[1][q] = ok ? (CT)f1[k] : (CT)0;
-      b[2][q] = ok ? (CT)f2[k] : (CT)0;
-      if (NIN == 4) b[NIN - 1][q] = ok ? (CT)f3[k] : (CT)0;
+      for (int q = 0; q < NP; ++q) {
+        const int l = 1 + q * RPP + lr;
+        const int co = c * W + lc - l;
+        const bool ok = (l <= rows) && (co >= 0) && (co < nx);
+        const size_t k = ok ? (size_t)grow(l) * nx + gcol(co) : 0;
+        b[0][q] = ok ? (CT)p.v[k] : (CT)0;
+        b[1][q] = ok ? (CT)f1[k] : (CT)0;
+        b[2][q] = ok ? (CT)f2[k] : (CT)0;
+        if (NIN == 4) b[NIN - 1][q] = ok ? (CT)f3[k] : (CT)0;
+      }
+      lds_wait_ge(&s_computed, c - NC + 1);   // ring slot free
+      const int sl = c % NC;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int l = 1 + q * RPP + lr;
+        if (l < L) {
+#pragma unroll
+          for (int m = 0; m < NIN; ++m) s_in[sl][m][l][lc] = b[m][q];
+        }
+      }
+      lds_put(&s_loaded[sl], c + 1);
     }
-  };
-  // ghost row (tile row 0) for chunk c: last row of the previous strip at
-  // sweep columns c*W + lcol (lanes with lrow == 0)
-  auto ghost_need = [&](int c) {
-    const int co = c * W + lcol;
-    return has_prev && lrow == 0 && co < nx;
-  };
-  auto ghost_prefetch = [&](int c) -> uint64_t {
-    return ghost_need(c) ? handoff_get(ho_in + gcol(c * W + lcol)) : 0ull;
-  };
-  auto to_lds = [&](CT (&b)[NIN][NP], int c, uint64_t gpre) {
-    const bool need = ghost_need(c);
-    const double gv = handoff_take(ho_in + (need ? gcol(c * W + lcol) : 0), need, gpre, p.sync.err, dead);
+  } else if (wave == 1) {
+    // ------------------------------------------------------------- poller
+    // One relaxed load per lane covers a window of 64 / W chunks; every
+    // complete chunk at the front of the window is delivered, the rest is
+    // polled again, so one memory round trip moves up to 64 / W chunks.
+    if (has_prev) {
+      constexpr int CPW = 64 / W;   // chunks per window
+      const uint64_t *ho_in = p.sync.handoff + (size_t)(strip - 1) * nx;
+      unsigned idle = 0;
+      bool dead = false;
+      int next = 0;
+      while (next < nchunks) {
+        const int co = next * W + lane;
+        const bool need = co < nx && next + lane / W < nchunks;
+        uint64_t b = need ? handoff_get(ho_in + gcol(co)) : 0ull;
+        if (dead && need && b == HANDOFF_EMPTY) b = 0;   // a failed wait delivers zeros
+        const uint64_t okm = __builtin_amdgcn_ballot_w64(!need || b != HANDOFF_EMPTY);
+        int nready = 0;
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const int l = q * RPP + lrow;
-      if (l < L) {
-#pragma unroll
-        for (int m = 0; m < NIN; ++m) s_in[m][l][lcol] = b[m][q];
+        for (int q = 0; q < CPW; ++q) {
+          const uint64_t g = (okm >> (q * W)) & ((W == 64) ? ~0ull : ((1ull << W) - 1));
+          if (nready == q && g == ((W == 64) ? ~0ull : ((1ull << W) - 1)) && next + q < nchunks) nready = q + 1;
+        }
+        for (int q = 0; q < nready; ++q) {
+          const int c = next + q;
+          lds_wait_ge(&s_computed, c - NC + 1);
+          if (lane / W == q) s_in[c % NC][0][0][lane % W] = (CT)__longlong_as_double((long long)b);
+          lds_put(&s_ghost[c % NC], c + 1);
+        }
+        if (need && lane / W < nready)   // consumed: empty again for the next launch
+          __hip_atomic_store(const_cast<uint64_t *>(ho_in + gcol(co)), HANDOFF_EMPTY, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        next += nready;
+        if (nready == 0) {
+          if (++idle > SPIN_LIMIT && !dead) {
+            dead = true;
+            if (lane == 0) atomicOr(p.sync.err, 1);
+          }
+          __builtin_amdgcn_s_sleep(1);
+        } else {
+          idle = 0;
+        }
       }
     }
-    if (lrow == 0) {
-      s_in[0][0][lcol] = (CT)gv;
-      if (OP == 1) s_in[3][0][lcol] = (CT)1;
-    }
-  };
-
-  CT west = (CT)0;
-  auto compute = [&](int c) {
-    const int lr = lane < L ? lane : L - 1;
-    const int pub_lane = has_next ? rows : -1;
+  } else if (wave == 2) {
+    // ------------------------------------------------------------- storer
+    for (int c = 0; c < nchunks; ++c) {
+      lds_wait_ge(&s_computed, c + 1);
+      const int b = c & 1;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const CT a0 = s_in[0][lr][w], a1 = s_in[1][lr][w], a2 = s_in[2][lr][w];
-      const CT south = dpp_up(west);
-      CT v = fma(-a2, south, fma(-a1, west, a0));
-      if (OP == 1) v = v * s_in[NIN - 1][lr][w];
-      if (lane < L) s_out[lane][w] = (double)v;
-      west = v;
-      if (lane == pub_lane) {
-        const int co = c * W + w - rows;
-        if (co >= 0 && co < nx) handoff_put(ho_out + gcol(co), (double)v);
+      for (int q = 0; q < NP; ++q) {
+        const int l = 1 + q * RPP + lr;
+        const int co = c * W + lc - l;
+        const bool ok = (l <= rows) && (co >= 0) && (co < nx);
+        if (ok) p.out[(size_t)grow(l) * nx + gcol(co)] = s_out[b][l][lc];
       }
+      lds_put(&s_stored, c + 1);
     }
-  };
-  auto store = [&](int c) {
+  } else {
+    // ------------------------------------------------------------- compute
+    uint64_t *ho_out = p.sync.handoff + (size_t)strip * nx;
+    const int row = lane < L ? lane : L - 1;
+    CT west = (CT)0;
+    for (int c = 0; c < nchunks; ++c) {
+      const int sl = c % NC;
+      lds_wait_eq(&s_loaded[sl], c + 1);
+      if (has_prev) lds_wait_eq(&s_ghost[sl], c + 1);
+      CT res[W];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const int l = q * RPP + lrow;
-      const int co = c * W + lcol - l;
-      const bool ok = (l >= 1) && (l <= rows) && (co >= 0) && (co < nx);
-      if (ok) p.out[(size_t)grow(l) * nx + gcol(co)] = s_out[l][lcol];
-    }
-  };
-
-  issue(stg0, 0);
-  if (nchunks > 1) issue(stg1, 1);
-  uint64_t g0 = ghost_prefetch(0), g1 = 0;
-  for (int c = 0; c < nchunks; c += 2) {
-    to_lds(stg0, c, g0);
-    if (c + 1 < nchunks) g1 = ghost_prefetch(c + 1);
-    if (c + 2 < nchunks) issue(stg0, c + 2);
-    __syncthreads();
-    compute(c);
-    __syncthreads();
-    store(c);
-    __syncthreads();
-    if (c + 1 < nchunks) {
-      to_lds(stg1, c + 1, g1);
-      if (c + 2 < nchunks) g0 = ghost_prefetch(c + 2);
-      if (c + 3 < nchunks) issue(stg1, c + 3);
-      __syncthreads();
-      compute(c + 1);
-      __syncthreads();
-      store(c + 1);
-      __syncthreads();
+      for (int w = 0; w < W; ++w) {
+        const CT a0 = s_in[sl][0][row][w], a1 = s_in[sl][1][row][w], a2 = s_in[sl][2][row][w];
+        const CT south = dpp_up(west);
+        CT v = fma(-a2, south, fma(-a1, west, a0));
+        if (OP == 1) v = v * s_in[sl][NIN - 1][row][w];
+        res[w] = v;
+        west = v;
+      }
+      lds_wait_ge(&s_stored, c - 1);   // output buffer c & 1 is free
+      const int b = c & 1;
+      if (lane < L) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) s_out[b][lane][w] = (double)res[w];
+      }
+      if (has_next) {
+        // publish this strip's last row: sweep columns c*W + w - rows
+        const int co = c * W + lane - rows;
+        if (lane < W && co >= 0 && co < nx) handoff_put(ho_out + gcol(co), s_out[b][rows][lane]);
+      }
+      lds_put(&s_computed, c + 1);
     }
   }
+  __syncthreads();
   strip_finish(p.sync, p.nstrips);
 }
 
@@ -402,15 +490,11 @@ static hipError_t launch_sweep_t(int nx, int ny, int rows, SweepParams p, hipStr
   switch (rows) {
     case 15:
       p.nstrips = strips_of(ny, 15);
-      hipLaunchKernelGGL((k_sweep<15, 32, OP, PREC>), dim3(p.nstrips), dim3(64), 0, s, p);
+      hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC>), dim3(p.nstrips), dim3(512), 0, s, p);
       break;
     case 31:
       p.nstrips = strips_of(ny, 31);
-      hipLaunchKernelGGL((k_sweep<31, 32, OP, PREC>), dim3(p.nstrips), dim3(64), 0, s, p);
-      break;
-    case 63:
-      p.nstrips = strips_of(ny, 63);
-      hipLaunchKernelGGL((k_sweep<63, 16, OP, PREC>), dim3(p.nstrips), dim3(64), 0, s, p);
+      hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC>), dim3(p.nstrips), dim3(1024), 0, s, p);
       break;
     default:
       return hipErrorInvalidValue;

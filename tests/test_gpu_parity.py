@@ -93,7 +93,7 @@ def test_dot_bitwise(adr, n):
     assert adr.dot(cuda(x), cuda(y)) == orc.dot(x, y)
 
 
-@pytest.mark.parametrize("rows", [15, 31, 63])
+@pytest.mark.parametrize("rows", [15, 31])
 @pytest.mark.parametrize("nx,ny,scheme,bc,eps", [
     (64, 64, 0, 0, 0.1), (37, 53, 1, 1, 2.0), (1, 40, 1, 0, 0.5), (45, 1, 0, 0, 0.5),
     (130, 67, 1, 0, 0.01), (33, 140, 0, 1, 1.0), (200, 200, 1, 0, 0.05)])
@@ -149,7 +149,7 @@ def test_solve_small_config_parity(adr, scheme):
     assert orc.max_error(P, x) == pytest.approx(orc.max_error(P, ref.x), rel=1e-6)
 
 
-@pytest.mark.parametrize("rows", [15, 31, 63])
+@pytest.mark.parametrize("rows", [15, 31])
 @pytest.mark.parametrize("nx,ny,scheme,bc,eps,X,Y", [
     (127, 129, 0, 0, 0.01, 1.0, 1.0), (100, 80, 1, 1, 2.0, 1.0, 1.0), (257, 130, 1, 0, 0.05, 2.0, 1.0),
     (19, 19, 0, 1, 4.0, 4.0, 4.0), (5, 300, 1, 0, 0.2, 1.0, 1.0)])
