@@ -138,13 +138,21 @@ __device__ __forceinline__ void lds_wait_ge(int *c, int target) {
 __device__ __forceinline__ void lds_wait_eq(int *c, int target) {
   while (lds_get(c) != target) __builtin_amdgcn_s_sleep(1);
 }
+// relaxed read of a {loaded, ghost} flag pair (one LDS access)
+__device__ __forceinline__ uint64_t lds_peek_pair(int *c) {
+  return __hip_atomic_load((uint64_t *)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int lds_peek(int *c) {
+  return __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local"); }
 
 template <int R, int NIN, int CTB>
 struct SweepShape {
   static constexpr int W = 16;                      // columns per chunk
   static constexpr int L = R + 1;                   // tile rows (row 0 = ghost)
   static constexpr int PITCH = W + 2;               // 16-byte aligned rows
-  static constexpr int NT = (R <= 15) ? 512 : 1024; // threads per workgroup
+  static constexpr int NT = 512;                    // threads per workgroup
   static constexpr int NLD = NT / 64 - 3;           // loader waves
   static constexpr int LDS_BUDGET = (R <= 15) ? 76 * 1024 : 150 * 1024;   // 2 or 1 workgroups per CU
   static constexpr int OUT_BYTES = 2 * L * PITCH * 8;
@@ -159,7 +167,7 @@ struct SweepShape {
 }  // namespace
 
 template <int R, int OP, int PREC>
-__global__ __launch_bounds__((R <= 15) ? 512 : 1024) void k_sweep_ws(SweepParams p) {
+__global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   using TF = typename std::conditional<PREC == 0, double, float>::type;
   using CT = typename std::conditional<PREC == 2, float, double>::type;
   constexpr int NIN = (OP == 0) ? 3 : 4;
@@ -169,7 +177,7 @@ __global__ __launch_bounds__((R <= 15) ? 512 : 1024) void k_sweep_ws(SweepParams
   static_assert(L <= 64, "strip too tall");
   __shared__ __align__(16) CT s_in[NC][NIN][L][PITCH];
   __shared__ __align__(16) double s_out[2][L][PITCH];
-  __shared__ int s_loaded[NC], s_ghost[NC];
+  __shared__ __align__(8) int s_flag[NC][2];   // [slot]{loaded, ghost}: chunk index + 1
   __shared__ int s_computed, s_stored;
   __shared__ int s_strip;
 
@@ -181,8 +189,8 @@ __global__ __launch_bounds__((R <= 15) ? 512 : 1024) void k_sweep_ws(SweepParams
     s_stored = 0;
   }
   if (tid < NC) {
-    s_loaded[tid] = 0;
-    s_ghost[tid] = 0;
+    s_flag[tid][0] = 0;
+    s_flag[tid][1] = 0;
   }
   // ghost row of every ring slot: zero values and coefficients (invd = 1)
   for (int e = tid; e < NC * NIN * PITCH; e += NT) {
@@ -226,49 +234,67 @@ __global__ __launch_bounds__((R <= 15) ? 512 : 1024) void k_sweep_ws(SweepParams
           for (int m = 0; m < NIN; ++m) s_in[sl][m][l][lc] = b[m][q];
         }
       }
-      lds_put(&s_loaded[sl], c + 1);
+      lds_put(&s_flag[sl][0], c + 1);
     }
   } else if (wave == 1) {
     // ------------------------------------------------------------- poller
-    // One relaxed load per lane covers a window of 64 / W chunks; every
-    // complete chunk at the front of the window is delivered, the rest is
-    // polled again, so one memory round trip moves up to 64 / W chunks.
+    // One relaxed load per lane covers a window of 64 / W chunks; NS such
+    // samples are kept in flight, issued one after another, so a value that
+    // lands is seen about one memory round trip later.  Every complete chunk
+    // at the front of the window is delivered in order; the rest is polled
+    // again.
     if (has_prev) {
       constexpr int CPW = 64 / W;   // chunks per window
+      constexpr int NS = 1;         // samples in flight
+      constexpr uint64_t GM = (W == 64) ? ~0ull : ((1ull << W) - 1);
       const uint64_t *ho_in = p.sync.handoff + (size_t)(strip - 1) * nx;
       unsigned idle = 0;
       bool dead = false;
       int next = 0;
-      while (next < nchunks) {
+      int ws[NS];
+      uint64_t val[NS];
+      auto sample = [&](int k) {
+        ws[k] = next;
         const int co = next * W + lane;
-        const bool need = co < nx && next + lane / W < nchunks;
-        uint64_t b = need ? handoff_get(ho_in + gcol(co)) : 0ull;
-        if (dead && need && b == HANDOFF_EMPTY) b = 0;   // a failed wait delivers zeros
-        const uint64_t okm = __builtin_amdgcn_ballot_w64(!need || b != HANDOFF_EMPTY);
-        int nready = 0;
+        val[k] = (co < nx && next + lane / W < nchunks) ? handoff_get(ho_in + gcol(co)) : 0ull;
+      };
 #pragma unroll
-        for (int q = 0; q < CPW; ++q) {
-          const uint64_t g = (okm >> (q * W)) & ((W == 64) ? ~0ull : ((1ull << W) - 1));
-          if (nready == q && g == ((W == 64) ? ~0ull : ((1ull << W) - 1)) && next + q < nchunks) nready = q + 1;
-        }
-        for (int q = 0; q < nready; ++q) {
-          const int c = next + q;
-          lds_wait_ge(&s_computed, c - NC + 1);
-          if (lane / W == q) s_in[c % NC][0][0][lane % W] = (CT)__longlong_as_double((long long)b);
-          lds_put(&s_ghost[c % NC], c + 1);
-        }
-        if (need && lane / W < nready)   // consumed: empty again for the next launch
-          __hip_atomic_store(const_cast<uint64_t *>(ho_in + gcol(co)), HANDOFF_EMPTY, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        next += nready;
-        if (nready == 0) {
-          if (++idle > SPIN_LIMIT && !dead) {
-            dead = true;
-            if (lane == 0) atomicOr(p.sync.err, 1);
+      for (int k = 0; k < NS; ++k) sample(k);
+      while (next < nchunks) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const int w0 = ws[k];
+          const int co = w0 * W + lane;
+          const bool need = co < nx && w0 + lane / W < nchunks;
+          uint64_t b = val[k];
+          if (dead && need && b == HANDOFF_EMPTY) b = 0;   // a failed wait delivers zeros
+          const uint64_t okm = __builtin_amdgcn_ballot_w64(!need || b != HANDOFF_EMPTY);
+          const int before = next;
+#pragma unroll
+          for (int q = 0; q < CPW; ++q) {
+            const int c = w0 + q;
+            if (c == next && c < nchunks && ((okm >> (q * W)) & GM) == GM) {
+              lds_wait_ge(&s_computed, c - NC + 1);
+              if (lane / W == q) s_in[c % NC][0][0][lane % W] = (CT)__longlong_as_double((long long)b);
+              lds_put(&s_flag[c % NC][1], c + 1);
+              ++next;
+            }
           }
-          __builtin_amdgcn_s_sleep(1);
-        } else {
-          idle = 0;
+          // consumed slots are emptied again for the next launch
+          const int cl = w0 + lane / W;
+          if (need && cl >= before && cl < next)
+            __hip_atomic_store(const_cast<uint64_t *>(ho_in + gcol(co)), HANDOFF_EMPTY, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          if (next == before) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++idle > SPIN_LIMIT && !dead) {
+              dead = true;
+              if (lane == 0) atomicOr(p.sync.err, 1);
+            }
+          } else {
+            idle = 0;
+          }
+          if (next < nchunks) sample(k);
         }
       }
     }
@@ -291,21 +317,42 @@ __global__ __launch_bounds__((R <= 15) ? 512 : 1024) void k_sweep_ws(SweepParams
     uint64_t *ho_out = p.sync.handoff + (size_t)strip * nx;
     const int row = lane < L ? lane : L - 1;
     CT west = (CT)0;
+    uint64_t fl = lds_peek_pair(&s_flag[0][0]);
     for (int c = 0; c < nchunks; ++c) {
       const int sl = c % NC;
-      lds_wait_eq(&s_loaded[sl], c + 1);
-      if (has_prev) lds_wait_eq(&s_ghost[sl], c + 1);
+      const uint64_t want = has_prev ? ((uint64_t)(uint32_t)(c + 1) | ((uint64_t)(uint32_t)(c + 1) << 32))
+                                     : (uint64_t)(uint32_t)(c + 1);
+      const uint64_t mask = has_prev ? ~0ull : 0xffffffffull;
+      while ((fl & mask) != want) {
+        __builtin_amdgcn_s_sleep(1);
+        fl = lds_peek_pair(&s_flag[sl][0]);
+      }
+      lds_acquire();
+      fl = lds_peek_pair(&s_flag[(c + 1) % NC][0]);   // next chunk's flags, read ahead
+      int st = lds_peek(&s_stored);
+      // the whole chunk's inputs into registers first, so that LDS latency is
+      // paid once per chunk and not inside the dependent chain
+      CT in[NIN][W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+#pragma unroll
+        for (int m = 0; m < NIN; ++m) in[m][w] = s_in[sl][m][row][w];
+      }
+      __builtin_amdgcn_sched_barrier(0);
       CT res[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        const CT a0 = s_in[sl][0][row][w], a1 = s_in[sl][1][row][w], a2 = s_in[sl][2][row][w];
         const CT south = dpp_up(west);
-        CT v = fma(-a2, south, fma(-a1, west, a0));
-        if (OP == 1) v = v * s_in[sl][NIN - 1][row][w];
+        CT v = fma(-in[2][w], south, fma(-in[1][w], west, in[0][w]));
+        if (OP == 1) v = v * in[NIN - 1][w];
         res[w] = v;
         west = v;
       }
-      lds_wait_ge(&s_stored, c - 1);   // output buffer c & 1 is free
+      while (st < c - 1) {   // output buffer c & 1 is free
+        __builtin_amdgcn_s_sleep(1);
+        st = lds_peek(&s_stored);
+      }
+      lds_acquire();
       const int b = c & 1;
       if (lane < L) {
 #pragma unroll
@@ -494,7 +541,7 @@ static hipError_t launch_sweep_t(int nx, int ny, int rows, SweepParams p, hipStr
       break;
     case 31:
       p.nstrips = strips_of(ny, 31);
-      hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC>), dim3(p.nstrips), dim3(1024), 0, s, p);
+      hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC>), dim3(p.nstrips), dim3(512), 0, s, p);
       break;
     default:
       return hipErrorInvalidValue;
