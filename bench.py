@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--neumann-window", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     return ap.parse_args()
 
@@ -165,6 +166,27 @@ def main():
                     frac=round(kern[dom]["gbs"] / PEAK_HBM_GBS, 4), traffic=traffic,
                     bytes_per_unknown=BYTES[dom], unknowns_per_launch=N)
 
+    # ---- mixed precision: FP32-stored factors (FP64 or FP32 sweeps) ----
+    variants = {}
+    if args.variants:
+        log("mixed-precision variants")
+        ref_prob, ref = hot_path("centered")
+        xref = ref.x.clone()
+        for prec in ("fp32_factors", "fp32_sweeps"):
+            prob = adr.assemble(args.eps, 1.0, 1.0, n, n, "centered", "dirichlet")
+            if args.rows:
+                prob.set_sweep_rows(args.rows)
+            prob.ilu0(prec)
+            res = prob.solve(tol=args.tol, maxit=args.maxit)
+            d = float((res.x - xref).abs().max() / xref.abs().max())
+            variants[prec] = dict(status=int(res.status), iters=int(res.iters), solve_s=round(res.solve_ms / 1e3, 4),
+                                  speedup_vs_fp64=round(ref.solve_ms / res.solve_ms, 3) if res.solve_ms > 0 else None,
+                                  max_rel_diff_vs_fp64=d, fp64_iters=int(ref.iters))
+            log("  %s: status %d iters %d (fp64 %d) %.2f s (fp64 %.2f s) max-rel-diff %.2e" %
+                (prec, res.status, res.iters, ref.iters, res.solve_ms / 1e3, ref.solve_ms / 1e3, d))
+            del prob, res
+        del ref_prob, ref
+
     # ---- the Neumann variant over a fixed window of passes ----
     log("neumann window: %d passes" % args.neumann_window)
     neu = {}
@@ -211,7 +233,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "dtype": "f32" if args.precision == "fp32_sweeps" else "f64",
         "data": "synthetic",
         "config": {"workload": "advection-diffusion %dx%d, X=Y=1, eps=%g, upwind+centered, "
                                "Dirichlet substitute for the Neumann mix (which does not converge)" % (n, n, args.eps),
@@ -224,6 +246,7 @@ def main():
         "kernels": {k: {kk: round(vv, 2) for kk, vv in v.items()} for k, v in kern.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "mixed_precision": variants,
         "neumann_window": neu,
         "solves": solves,
     }

@@ -334,6 +334,47 @@ void or_usolve(int32_t nx, int32_t ny, const double *ue, const double *un,
   }
 }
 
+/* The same two substitutions carried out in single precision (the mixed-
+ * precision preconditioner in which the factors are stored in FP32 and the
+ * triangular solves themselves run in FP32): inputs are rounded to float,
+ * every operation is a float operation in the fixed fma order above, and the
+ * result is widened back to double.  Factors are given as doubles holding
+ * float values. */
+void or_lsolve_f32(int32_t nx, int32_t ny, const double *lw, const double *ls,
+                   const double *q, double *y) {
+  const size_t n = (size_t)nx * (size_t)ny;
+  float *yf = malloc(sizeof(float) * (n ? n : 1));
+  for (size_t k = 0; k < n; ++k) {
+    const int32_t i = (int32_t)(k % (size_t)nx);
+    const int32_t j = (int32_t)(k / (size_t)nx);
+    const float yw = (i > 0) ? yf[k - 1] : 0.0f;
+    const float ys = (j > 0) ? yf[k - nx] : 0.0f;
+    float t = fmaf(-(float)lw[k], yw, (float)q[k]);
+    t = fmaf(-(float)ls[k], ys, t);
+    yf[k] = t;
+    y[k] = (double)t;
+  }
+  free(yf);
+}
+
+void or_usolve_f32(int32_t nx, int32_t ny, const double *ue, const double *un,
+                   const double *invd, const double *y, double *z) {
+  const size_t n = (size_t)nx * (size_t)ny;
+  float *zf = malloc(sizeof(float) * (n ? n : 1));
+  for (size_t kk = n; kk-- > 0;) {
+    const int32_t i = (int32_t)(kk % (size_t)nx);
+    const int32_t j = (int32_t)(kk / (size_t)nx);
+    const float ze = (i < nx - 1) ? zf[kk + 1] : 0.0f;
+    const float zn = (j < ny - 1) ? zf[kk + nx] : 0.0f;
+    float t = fmaf(-(float)ue[kk], ze, (float)y[kk]);
+    t = fmaf(-(float)un[kk], zn, t);
+    t = t * (float)invd[kk];
+    zf[kk] = t;
+    z[kk] = (double)t;
+  }
+  free(zf);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Inner products in double-double arithmetic.                              */
 /* ------------------------------------------------------------------------ */
@@ -420,6 +461,8 @@ typedef struct {
  * Fixed update formulas: p = fma(beta, fma(-omega, v, p), r),
  * s = fma(-alpha, v, r), x = fma(omega, z, fma(alpha, p^, x)),
  * r = fma(-omega, t, s); r0 = b - A x0 by plain subtraction.
+ * sweep_f32 = 1 applies M^{-1} with the single-precision substitutions
+ * (or_lsolve_f32 / or_usolve_f32); the factors must then hold float values.
  * x0 may be NULL (zero guess).  hist_l2/hist_max hold maxit+1 entries:
  * entry 0 is ||r0||, entry i the recursively updated ||r_i|| after pass i, or
  * ||s|| at a half-step exit. */
@@ -428,6 +471,7 @@ int or_bicgstab(int32_t nx, int32_t ny,
                 const double *lw, const double *ls, const double *invd,
                 const double *ue, const double *un,
                 const double *b, const double *x0, double tol, int32_t abs_tol, int32_t maxit,
+                int32_t sweep_f32,
                 double *x, double *hist_l2, double *hist_max, or_solve_info *info) {
   const int64_t n = (int64_t)nx * (int64_t)ny;
   memset(info, 0, sizeof(*info));
@@ -474,8 +518,13 @@ int or_bicgstab(int32_t nx, int32_t ny,
       const double beta = (rho / rho_prev) * (alpha / omega);
       for (int64_t k = 0; k < n; ++k) p[k] = fma(beta, fma(-omega, v[k], p[k]), r[k]);
     }
-    or_lsolve(nx, ny, lw, ls, p, yy);
-    or_usolve(nx, ny, ue, un, invd, yy, ph);
+    if (sweep_f32) {
+      or_lsolve_f32(nx, ny, lw, ls, p, yy);
+      or_usolve_f32(nx, ny, ue, un, invd, yy, ph);
+    } else {
+      or_lsolve(nx, ny, lw, ls, p, yy);
+      or_usolve(nx, ny, ue, un, invd, yy, ph);
+    }
     or_spmv(nx, ny, S, W, C, E, N, ph, v);
     alpha = rho / or_dot(n, rh, v);
     if (!isfinite(alpha)) { status = OR_NONFINITE; break; }
@@ -491,8 +540,13 @@ int or_bicgstab(int32_t nx, int32_t ny,
       status = OR_OK;
       break;
     }
-    or_lsolve(nx, ny, lw, ls, s, yy);
-    or_usolve(nx, ny, ue, un, invd, yy, z);
+    if (sweep_f32) {
+      or_lsolve_f32(nx, ny, lw, ls, s, yy);
+      or_usolve_f32(nx, ny, ue, un, invd, yy, z);
+    } else {
+      or_lsolve(nx, ny, lw, ls, s, yy);
+      or_usolve(nx, ny, ue, un, invd, yy, z);
+    }
     or_spmv(nx, ny, S, W, C, E, N, z, t);
     const double ts = or_dot(n, t, s), tt = or_dot(n, t, t);
     omega = ts / tt;

@@ -55,8 +55,10 @@ def lib():
         L.or_maxabs.restype = f64
         L.or_maxabs.argtypes = [i64, _D]
         L.or_bicgstab.restype = ctypes.c_int
-        L.or_bicgstab.argtypes = ([i32, i32] + [_D] * 10 + [_D, _D, f64, i32, i32, _D, _D, _D,
+        L.or_bicgstab.argtypes = ([i32, i32] + [_D] * 10 + [_D, _D, f64, i32, i32, i32, _D, _D, _D,
                                                              ctypes.POINTER(_Info)])
+        L.or_lsolve_f32.argtypes = [i32, i32] + [_D] * 4
+        L.or_usolve_f32.argtypes = [i32, i32] + [_D] * 5
         L.or_max_error.restype = f64
         L.or_max_error.argtypes = [f64, f64, i32, i32, i32, _D, _D]
         _lib = L
@@ -185,6 +187,27 @@ def usolve(nx, ny, F, y):
     return z
 
 
+def lsolve_f32(nx, ny, F, q):
+    q = _f64(q)
+    y = np.zeros(nx * ny)
+    lib().or_lsolve_f32(nx, ny, _p(F.lw), _p(F.ls), _p(q), _p(y))
+    return y
+
+
+def usolve_f32(nx, ny, F, y):
+    y = _f64(y)
+    z = np.zeros(nx * ny)
+    lib().or_usolve_f32(nx, ny, _p(F.ue), _p(F.un), _p(F.invd), _p(y), _p(z))
+    return z
+
+
+def round_factors_f32(F):
+    """The factors as the mixed-precision preconditioner stores them: every
+    entry rounded to the nearest float (kept in float64 arrays)."""
+    r = lambda a: a.astype(np.float32).astype(np.float64)
+    return Factors(r(F.lw), r(F.ls), r(F.invd), r(F.ue), r(F.un), F.status, F.bad)
+
+
 def dot(x, y):
     x, y = _f64(x).ravel(), _f64(y).ravel()
     return lib().or_dot(x.size, _p(x), _p(y))
@@ -207,7 +230,7 @@ class Solve:
     true_relres: float
 
 
-def bicgstab(P, F, tol=1e-10, maxit=1000, x0=None, abs_tol=False, b=None):
+def bicgstab(P, F, tol=1e-10, maxit=1000, x0=None, abs_tol=False, b=None, sweep_f32=False):
     rhs = P.rhs if b is None else _f64(b)
     x = np.zeros(P.n)
     h2 = np.zeros(maxit + 1)
@@ -216,7 +239,7 @@ def bicgstab(P, F, tol=1e-10, maxit=1000, x0=None, abs_tol=False, b=None):
     x0p = None if x0 is None else _f64(x0)
     lib().or_bicgstab(P.nx, P.ny, _p(P.S), _p(P.W), _p(P.C), _p(P.E), _p(P.N),
                       _p(F.lw), _p(F.ls), _p(F.invd), _p(F.ue), _p(F.un),
-                      _p(rhs), _p(x0p), float(tol), int(bool(abs_tol)), int(maxit),
+                      _p(rhs), _p(x0p), float(tol), int(bool(abs_tol)), int(maxit), int(bool(sweep_f32)),
                       _p(x), _p(h2), _p(hm), ctypes.byref(info))
     hl = info.hist_len
     return Solve(x, h2[:hl].copy(), hm[:hl].copy(), info.status, info.iters,

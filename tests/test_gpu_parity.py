@@ -255,3 +255,51 @@ def test_full_size_prefix_parity(adr, scheme):
     assert np.array_equal(res.hist_l2, ref.hist_l2)
     assert np.array_equal(res.hist_max, ref.hist_max)
     assert equal(x, ref.x)
+
+
+@pytest.mark.parametrize("rows", [15, 31])
+@pytest.mark.parametrize("precision", ["fp32_factors", "fp32_sweeps"])
+def test_mixed_precision_precond_bitwise(adr, rows, precision):
+    """FP32-stored factors (rounded from the FP64 ILU(0)) applied with FP64
+    or FP32 sweep arithmetic equal the oracle's substitutions of the same
+    float factors."""
+    say("mixed precond", rows, precision)
+    nx, ny = 150, 97
+    prob = adr.assemble(0.02, 1.0, 1.0, nx, ny, 1, 0)
+    prob.set_sweep_rows(rows)
+    prob.ilu0(precision)
+    P = oracle_problem(0.02, 1.0, 1.0, nx, ny, 1, 0)
+    F = orc.round_factors_f32(orc.ilu0(P))
+    q = np.random.default_rng(9).standard_normal(nx * ny)
+    z = host(prob.precond(cuda(q)))
+    if precision == "fp32_factors":
+        zo = orc.usolve(nx, ny, F, orc.lsolve(nx, ny, F, q))
+    else:
+        zo = orc.usolve_f32(nx, ny, F, orc.lsolve_f32(nx, ny, F, q))
+    assert equal(z, zo)
+
+
+@pytest.mark.parametrize("precision", ["fp32_factors", "fp32_sweeps"])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_mixed_precision_solve(adr, precision, scheme):
+    """Mixed-precision solves match the oracle run in the same mode, and their
+    error against the FP64 oracle solution is stated (and bounded)."""
+    say("mixed solve", precision, scheme)
+    n, eps = 200, 0.01
+    prob = adr.assemble(eps, 1.0, 1.0, n, n, scheme, 0)
+    prob.ilu0(precision)
+    res = prob.solve(1e-10, 3000)
+    x = host(res.x)
+    P = oracle_problem(eps, 1.0, 1.0, n, n, scheme, 0)
+    F = orc.ilu0(P)
+    ref = orc.bicgstab(P, orc.round_factors_f32(F), tol=1e-10, maxit=3000, sweep_f32=(precision == "fp32_sweeps"))
+    ref64 = orc.bicgstab(P, F, tol=1e-10, maxit=3000)
+    assert res.status == ref.status == orc.OK
+    assert abs(res.iters - ref.iters) <= 2
+    assert maxrel(x, ref.x) <= 1e-9
+    err64 = maxrel(x, ref64.x)
+    say("  iters %d (fp64 oracle %d), max-rel-diff vs fp64 oracle %.2e" % (res.iters, ref64.iters, err64))
+    assert err64 <= 1e-6
+    # the discretisation error is within 1% of the FP64 oracle's
+    e_mixed, e64 = orc.max_error(P, x), orc.max_error(P, ref64.x)
+    assert abs(e_mixed - e64) <= 0.01 * e64

@@ -453,3 +453,35 @@ def test_forcing_field_is_added_with_relative_amplitude(orc):
     dx, dy = 1.0 / (nx + 1), 1.0 / (ny + 1)
     np.testing.assert_allclose(P1.rhs - P0.rhs, 0.1 * np.abs(fman).max() * g * dx * dx * dy * dy,
                                rtol=1e-9, atol=1e-20)
+
+
+# --------------------------------------------------------------------------
+# Mixed precision: factors stored in FP32, sweeps in FP64 or FP32
+# --------------------------------------------------------------------------
+
+def test_single_precision_sweeps_are_single_precision_solves(orc):
+    """The FP32 substitutions agree with the FP64 substitutions of the same
+    (float-rounded) factors to single-precision accuracy, and exactly invert
+    their own triangular factors up to float rounding."""
+    P = orc.assemble(0.05, 1.0, 1.0, 24, 20, core.CENTERED, core.DIRICHLET)
+    F = orc.round_factors_f32(orc.ilu0(P))
+    q = np.random.default_rng(2).standard_normal(P.n)
+    y64 = orc.lsolve(P.nx, P.ny, F, q)
+    y32 = orc.lsolve_f32(P.nx, P.ny, F, q)
+    assert np.abs(y32 - y64).max() <= 1e-5 * np.abs(y64).max()
+    assert np.all(y32 == y32.astype(np.float32))       # values are floats
+    z64 = orc.usolve(P.nx, P.ny, F, y32)
+    z32 = orc.usolve_f32(P.nx, P.ny, F, y32)
+    assert np.abs(z32 - z64).max() <= 1e-4 * np.abs(z64).max()
+
+
+@pytest.mark.parametrize("sweep_f32", [False, True])
+def test_mixed_precision_preconditioner_still_reaches_the_fp64_solution(orc, sweep_f32):
+    """A lower-precision M only changes the convergence rate: the FP64 outer
+    iteration still reaches ||r|| < 1e-13 ||b|| and the dense LU solution."""
+    P = orc.assemble(0.1, 1.0, 1.0, 16, 16, core.UPWIND, core.DIRICHLET)
+    F = orc.round_factors_f32(orc.ilu0(P))
+    s = orc.bicgstab(P, F, tol=1e-13, maxit=500, sweep_f32=sweep_f32)
+    assert s.status == core.OK
+    ref = dense.exact_discrete(P)
+    assert np.abs(s.x - ref).max() <= 1e-11 * np.abs(ref).max()
