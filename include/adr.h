@@ -158,6 +158,50 @@ adr_status adr_bicgstab_solve(adr_problem *p, double tol, int32_t maxit,
 void adr_destroy(adr_problem *p);
 
 /* ---------------------------------------------------------------------------
+ * Batches: many independent instances (each its own eps, X, Y, nx, ny,
+ * scheme, bc) held in one problem and advanced together by the same kernel
+ * launches -- one launch per step of the method covers every instance, so
+ * small grids share the GPU and the wavefront latency of one instance is
+ * hidden behind the others.  Instance k occupies elements
+ * [offset[k], offset[k+1]) of every batched vector (adr_batch_layout), in the
+ * per-instance order described above.  A single-instance problem is a batch
+ * of one; the single-instance calls above accept only count == 1.
+ * ------------------------------------------------------------------------- */
+
+/* Section 4 assembly of `count` instances (arrays of `count` entries; the
+ * argument rules of adr_assemble apply to each).  field_dev: NULL or a
+ * batched device vector added to each instance's manufactured forcing with
+ * amplitude amp * max|f_man| of that instance. */
+adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X, const double *Y,
+                              const int32_t *nx, const int32_t *ny, const int32_t *scheme,
+                              const int32_t *bc, const double *field_dev, double amp,
+                              void *stream, adr_problem **out);
+
+/* Number of instances and their offsets (count + 1 entries; the last is the
+ * total length of a batched vector).  Either output may be NULL. */
+adr_status adr_batch_layout(const adr_problem *p, int32_t *count, int64_t *offsets);
+
+/* ILU(0) of every instance (Section 5.1), one launch for the batch.
+ * bad_index: NULL or `count` entries (-1, or the first zero pivot). */
+adr_status adr_batch_ilu0(adr_problem *p, int32_t precision, int64_t *bad_index);
+
+/* BiCGSTAB (Section 5.2) on every instance with the same tol and maxit; each
+ * instance stops on its own tests and is skipped by later launches.
+ * x0_dev / x_dev: batched device vectors (x0 may be NULL).
+ * hist_l2, hist_max: NULL or count*(maxit+1) host doubles, instance-major.
+ * info: NULL or `count` records (solve_ms is the batch's time).
+ * Returns ADR_OK if every instance reached the tolerance, else the status of
+ * the first instance that did not, or a call error. */
+adr_status adr_batch_solve(adr_problem *p, double tol, int32_t maxit, const double *x0_dev,
+                           double *x_dev, double *hist_l2, double *hist_max, adr_solve_info *info);
+
+/* Sweep-schedule autotuner: times M^{-1} on the problem's right-hand sides
+ * for every supported strip height, keeps the fastest and returns it (and the
+ * time of one application in ms).  Needs adr_ilu0 / adr_batch_ilu0 first;
+ * results do not depend on the choice. */
+adr_status adr_autotune(adr_problem *p, int32_t *rows_chosen, double *ms_per_apply);
+
+/* ---------------------------------------------------------------------------
  * Inspection and single-step entry points (the same kernels the solve uses).
  * ------------------------------------------------------------------------- */
 

@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import (OK, MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE, UPWIND, CENTERED,
                    DIRICHLET, NEUMANN_XY, FP64, FP32_FACTORS, FP32_SWEEPS, AdrError)
 
-__all__ = ["assemble", "Problem", "SolveResult", "dot", "AdrError", "OK", "MAXIT", "BREAKDOWN_RHO",
+__all__ = ["assemble", "assemble_batch", "Problem", "Batch", "SolveResult", "BatchResult", "dot", "AdrError", "OK", "MAXIT", "BREAKDOWN_RHO",
            "OMEGA_ZERO", "ZERO_PIVOT", "NONFINITE", "UPWIND", "CENTERED", "DIRICHLET", "NEUMANN_XY",
            "FP64", "FP32_FACTORS", "FP32_SWEEPS"]
 
@@ -182,6 +182,108 @@ def assemble(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet", field=None, amp
     _lib.check(L.adr_assemble(float(eps), float(X), float(Y), int(nx), int(ny), sch, b, fp, float(amp),
                               sh, ctypes.byref(h)))
     return Problem(h, float(eps), float(X), float(Y), int(nx), int(ny), sch, b, stream)
+
+
+@dataclass
+class BatchResult:
+    x: object              # batched CUDA float64 tensor
+    status: np.ndarray     # per instance
+    iters: np.ndarray
+    half_step: np.ndarray
+    hist_l2: list          # per instance arrays
+    hist_max: list
+    bnorm: np.ndarray
+    true_relres: np.ndarray
+    solve_ms: float
+    overall: int           # adr_batch_solve's return value
+
+
+class Batch:
+    """Many independent instances advanced together (adr_batch_* calls)."""
+
+    def __init__(self, handle, params, stream):
+        self._h = handle
+        self.params = params
+        self._stream = stream
+        L = _lib.load()
+        cnt = ctypes.c_int32(0)
+        _lib.check(L.adr_batch_layout(self._h, ctypes.byref(cnt), None))
+        self.count = cnt.value
+        offs = (ctypes.c_int64 * (self.count + 1))()
+        _lib.check(L.adr_batch_layout(self._h, None, offs))
+        self.offsets = np.array(offs[:], dtype=np.int64)
+        self.n = int(self.offsets[-1])
+        self.precision = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().adr_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    def ilu0(self, precision="fp64"):
+        prec = _PREC[precision]
+        bad = (ctypes.c_int64 * self.count)()
+        st = _lib.check(_lib.load().adr_batch_ilu0(self._h, prec, bad))
+        if st == ZERO_PIVOT:
+            raise AdrError(st, "zero pivot in instances %s" % [k for k in range(self.count) if bad[k] >= 0])
+        self.precision = prec
+        return self
+
+    def autotune(self):
+        rows = ctypes.c_int32(0)
+        ms = ctypes.c_double(0.0)
+        _lib.check(_lib.load().adr_autotune(self._h, ctypes.byref(rows), ctypes.byref(ms)))
+        return rows.value, ms.value
+
+    def set_sweep_rows(self, rows):
+        _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
+
+    def split(self, x):
+        """Per-instance views of a batched vector."""
+        return [x[self.offsets[k]:self.offsets[k + 1]] for k in range(self.count)]
+
+    def solve(self, tol=1e-10, maxit=1000, x0=None, out=None):
+        torch = _torch()
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        xp = _dev_f64(x, self.n, "out")
+        x0p = None if x0 is None else _dev_f64(x0, self.n, "x0")
+        h2 = np.zeros(self.count * (maxit + 1))
+        hm = np.zeros(self.count * (maxit + 1))
+        info = (_lib.SolveInfo * self.count)()
+        st = _lib.check(_lib.load().adr_batch_solve(self._h, float(tol), int(maxit), x0p, xp,
+                                                     _host_ptr(h2), _host_ptr(hm), info))
+        h2 = h2.reshape(self.count, maxit + 1)
+        hm = hm.reshape(self.count, maxit + 1)
+        return BatchResult(
+            x, np.array([i.status for i in info]), np.array([i.iters for i in info]),
+            np.array([bool(i.half_step) for i in info]),
+            [h2[k, :info[k].hist_len].copy() for k in range(self.count)],
+            [hm[k, :info[k].hist_len].copy() for k in range(self.count)],
+            np.array([i.bnorm for i in info]), np.array([i.true_relres for i in info]),
+            info[0].solve_ms if self.count else 0.0, st)
+
+
+def assemble_batch(eps, X, Y, nx, ny, scheme, bc, field=None, amp=0.0, stream=None):
+    """Batched Section 4 assembly (adr_batch_assemble).  Every argument but
+    field/amp/stream is a sequence with one entry per instance; field is an
+    optional batched CUDA float64 tensor."""
+    count = len(eps)
+    f64a = lambda v: (ctypes.c_double * count)(*[float(a) for a in v])
+    i32a = lambda v: (ctypes.c_int32 * count)(*[int(a) for a in v])
+    sch = [_SCHEMES[s_] for s_ in scheme]
+    bcs = [_BCS[b_] for b_ in bc]
+    total = int(sum(int(a) * int(b) for a, b in zip(nx, ny)))
+    fp = None if field is None else _dev_f64(field, total, "field")
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().adr_batch_assemble(count, f64a(eps), f64a(X), f64a(Y), i32a(nx), i32a(ny), i32a(sch),
+                                              i32a(bcs), fp, float(amp), _stream_handle(stream), ctypes.byref(h)))
+    params = [dict(eps=float(eps[k]), X=float(X[k]), Y=float(Y[k]), nx=int(nx[k]), ny=int(ny[k]), scheme=sch[k],
+                   bc=bcs[k]) for k in range(count)]
+    return Batch(h, params, stream)
 
 
 def dot(x, y, stream=None):

@@ -18,7 +18,8 @@ FP64, FP32_FACTORS, FP32_SWEEPS = 0, 1, 2
 EXPORTS = [
     "adr_assemble", "adr_ilu0", "adr_bicgstab_solve", "adr_destroy", "adr_get_dia", "adr_set_dia",
     "adr_get_factors", "adr_spmv", "adr_precond", "adr_lsolve", "adr_usolve", "adr_dot", "adr_device_bytes",
-    "adr_set_sweep_rows", "adr_status_str", "adr_last_error",
+    "adr_set_sweep_rows", "adr_status_str", "adr_last_error", "adr_batch_assemble", "adr_batch_layout",
+    "adr_batch_ilu0", "adr_batch_solve", "adr_autotune",
 ]
 
 
@@ -70,6 +71,18 @@ def load():
     L.adr_device_bytes.argtypes = [P]
     L.adr_set_sweep_rows.restype = ctypes.c_int
     L.adr_set_sweep_rows.argtypes = [P, i32]
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    I64P = ctypes.POINTER(ctypes.c_int64)
+    L.adr_batch_assemble.restype = ctypes.c_int
+    L.adr_batch_assemble.argtypes = [i32, D, D, D, I32P, I32P, I32P, I32P, P, f64, P, ctypes.POINTER(P)]
+    L.adr_batch_layout.restype = ctypes.c_int
+    L.adr_batch_layout.argtypes = [P, I32P, I64P]
+    L.adr_batch_ilu0.restype = ctypes.c_int
+    L.adr_batch_ilu0.argtypes = [P, i32, I64P]
+    L.adr_batch_solve.restype = ctypes.c_int
+    L.adr_batch_solve.argtypes = [P, f64, i32, P, P, D, D, ctypes.POINTER(SolveInfo)]
+    L.adr_autotune.restype = ctypes.c_int
+    L.adr_autotune.argtypes = [P, I32P, D]
     L.adr_status_str.restype = ctypes.c_char_p
     L.adr_status_str.argtypes = [i32]
     L.adr_last_error.restype = ctypes.c_char_p

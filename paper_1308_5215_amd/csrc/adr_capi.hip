@@ -1,9 +1,11 @@
 // Host runtime and C ABI (include/adr.h): argument checking, device memory,
-// the 1-D tables of the discretisation, and the BiCGSTAB driver, which
-// captures a chunk of passes into a HIP graph and replays it until the
-// device-side state reports that the solve has stopped.
+// the 1-D tables of the discretisation, batch geometry, the sweep-height
+// autotuner and the BiCGSTAB driver, which captures a chunk of passes into a
+// HIP graph and replays it until the device-side states report that every
+// instance has stopped.  A single problem is a batch of one instance.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -33,14 +35,14 @@ adr_status fail(adr_status st, const char *fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                     \
-  do {                                                                                    \
-    hipError_t e_ = (expr);                                                               \
-    if (e_ != hipSuccess) {                                                               \
-      (void)hipGetLastError();                                                            \
-      return fail(e_ == hipErrorOutOfMemory ? ADR_ERR_NOMEM : ADR_ERR_DEVICE, "%s: %s (%s:%d)", \
-                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
-    }                                                                                     \
+#define HIP_TRY(expr)                                                                               \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) {                                                                         \
+      (void)hipGetLastError();                                                                      \
+      return fail(e_ == hipErrorOutOfMemory ? ADR_ERR_NOMEM : ADR_ERR_DEVICE, "%s: %s (%s:%d)", #expr, \
+                  hipGetErrorString(e_), __FILE__, __LINE__);                                       \
+    }                                                                                               \
   } while (0)
 
 FastDiv make_fastdiv(uint32_t d) {
@@ -53,16 +55,20 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
+// Streaming geometry of one instance: at most ~2048 blocks of 256 threads.
+void stream_geom(int64_t n, int &chunk, int &nblk) {
+  int64_t c = (n + 2047) / 2048;
+  c = ((c + 255) / 256) * 256;
+  if (c < 256) c = 256;
+  chunk = (int)c;
+  nblk = (int)((n + c - 1) / c);
+  if (nblk < 1) nblk = 1;
+}
+
 Stream1D make_geom(int64_t n) {
   Stream1D g;
   g.n = (int)n;
-  const int64_t target = 2048;
-  int64_t chunk = (n + target - 1) / target;
-  chunk = ((chunk + 255) / 256) * 256;
-  if (chunk < 256) chunk = 256;
-  g.chunk = (int)chunk;
-  g.nblk = (int)((n + chunk - 1) / chunk);
-  if (g.nblk < 1) g.nblk = 1;
+  stream_geom(n, g.chunk, g.nblk);
   return g;
 }
 
@@ -80,9 +86,8 @@ void dfree(T *&p) {
   p = nullptr;
 }
 
-int auto_rows(int ny) {
-  return ny >= 2048 ? 31 : 15;
-}
+// Strip height from the grid alone (used until the autotuner has run).
+int default_rows(int max_ny) { return max_ny >= 2048 ? 31 : 15; }
 
 }  // namespace
 
@@ -90,19 +95,20 @@ struct adr_problem {
   int dev = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;   // private stream used only for graph capture
-  double eps = 0, X = 0, Y = 0;
-  int nx = 0, ny = 0, scheme = 0, bc = 0;
-  int64_t n = 0;
+  int count = 0;
+  std::vector<double> eps, X, Y;
+  std::vector<int> nx, ny, scheme, bc;
+  std::vector<Inst> inst;      // host copy of the instance table
+  Inst *d_inst = nullptr;
+  int64_t ntot = 0;            // unknowns over the batch
+  int nblk = 0, nstrips = 0, rows = 0, max_ny = 0;
   size_t bytes = 0;
-  Stream1D geom{};
-  FastDiv fd{};
-  // matrix
+  // matrix (batched)
   double *S = nullptr, *W = nullptr, *C = nullptr, *E = nullptr, *N = nullptr, *rhs = nullptr;
   // factors
   double *lw = nullptr, *ls = nullptr, *invd = nullptr;
   float *lw32 = nullptr, *ls32 = nullptr, *invd32 = nullptr, *E32 = nullptr, *N32 = nullptr;
   int factored = 0, precision = 0;
-  int rows = 0;   // sweep strip height (0 = automatic)
   // iteration vectors
   double *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
   double *ph = nullptr, *z = nullptr, *y = nullptr;
@@ -110,14 +116,15 @@ struct adr_problem {
   double2 *partials = nullptr;
   SolveState *st = nullptr;
   double *hist = nullptr;
-  int hist_cap = 0;
-  double *scal = nullptr;      // scratch device scalars
+  int hist_cap = 0;   // maxit + 1 the history buffer was sized for
+  double *scal = nullptr;
   int64_t *bad = nullptr;
   // wavefront synchronisation
   unsigned *ticket = nullptr;
   uint64_t *handoff = nullptr;
+  int64_t handoff_words = 0;
   int *err = nullptr;
-  // host pinned mirror of the state
+  // host pinned mirror of the states
   SolveState *h_st = nullptr;
   // captured iteration chunk
   hipGraphExec_t gexec = nullptr;
@@ -125,21 +132,58 @@ struct adr_problem {
   double g_tol = -1;
   int g_maxit = -1, g_prec = -1, g_rows = -1, g_K = 0;
 
-  int sweep_rows() const { return rows ? rows : auto_rows(ny); }
   SweepSync sync() const { return SweepSync{ticket, handoff, err}; }
   Dia dia() const { return Dia{S, W, C, E, N}; }
+  BatchGeom geom() const { return BatchGeom{d_inst, count, nblk, nstrips, rows}; }
 };
 
 namespace {
 
+// (Re)build the instance table for strip height R and upload it.
+adr_status build_table(adr_problem *P, int R) {
+  int64_t off = 0, ho = 0;
+  int blk = 0, strip = 0;
+  for (int k = 0; k < P->count; ++k) {
+    Inst &I = P->inst[k];
+    I.nx = P->nx[k];
+    I.ny = P->ny[k];
+    I.n = I.nx * I.ny;
+    int nb;
+    stream_geom(I.n, I.chunk, nb);
+    I.off = off;
+    I.blk0 = blk;
+    I.nblk = (nb + 7) & ~7;   // whole XCD rounds: a block's XCD is its local index mod 8
+    I.strip0 = strip;
+    I.nstrips = (I.ny + R - 1) / R;
+    I.ho_off = ho;
+    I.fd = make_fastdiv((uint32_t)I.nx);
+    I.pad = 0;
+    off += I.n;
+    blk += I.nblk;
+    strip += I.nstrips;
+    ho += (int64_t)I.nstrips * I.nx;
+  }
+  P->ntot = off;
+  P->nblk = blk;
+  P->nstrips = strip;
+  P->rows = R;
+  if (!P->d_inst) HIP_TRY(dalloc(&P->d_inst, (size_t)P->count, P->bytes));
+  HIP_TRY(hipMemcpyAsync(P->d_inst, P->inst.data(), sizeof(Inst) * (size_t)P->count, hipMemcpyHostToDevice,
+                         P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return ADR_OK;
+}
+
 adr_status ensure_sync(adr_problem *P) {
   if (P->ticket) return ADR_OK;
-  const int64_t slots = (int64_t)((P->ny + 14) / 15 + 1) * P->nx;
+  int64_t words = 0;   // enough for the smallest strip height
+  for (int k = 0; k < P->count; ++k) words += (int64_t)((P->ny[k] + 14) / 15) * P->nx[k];
+  P->handoff_words = words;
   HIP_TRY(dalloc(&P->ticket, 2, P->bytes));
-  HIP_TRY(dalloc(&P->handoff, (size_t)slots, P->bytes));
+  HIP_TRY(dalloc(&P->handoff, (size_t)words, P->bytes));
   HIP_TRY(dalloc(&P->err, 1, P->bytes));
   HIP_TRY(launch_fill_u32(P->ticket, 2, 0u, P->stream));
-  HIP_TRY(launch_fill_u64(P->handoff, slots, HANDOFF_EMPTY, P->stream));
+  HIP_TRY(launch_fill_u64(P->handoff, words, HANDOFF_EMPTY, P->stream));
   HIP_TRY(hipMemsetAsync(P->err, 0, sizeof(int), P->stream));
   return ADR_OK;
 }
@@ -150,9 +194,8 @@ adr_status check_device_fault(adr_problem *P) {
   HIP_TRY(hipStreamSynchronize(P->stream));
   if (herr) {
     // a wavefront wait exceeded its spin limit: restore the sync memory
-    const int64_t slots = (int64_t)((P->ny + 14) / 15 + 1) * P->nx;
     HIP_TRY(launch_fill_u32(P->ticket, 2, 0u, P->stream));
-    HIP_TRY(launch_fill_u64(P->handoff, slots, HANDOFF_EMPTY, P->stream));
+    HIP_TRY(launch_fill_u64(P->handoff, P->handoff_words, HANDOFF_EMPTY, P->stream));
     HIP_TRY(hipMemsetAsync(P->err, 0, sizeof(int), P->stream));
     HIP_TRY(hipStreamSynchronize(P->stream));
     return fail(ADR_ERR_DEVICE, "wavefront hand-off wait exceeded its limit");
@@ -163,14 +206,14 @@ adr_status check_device_fault(adr_problem *P) {
 adr_status ensure_iter_buffers(adr_problem *P, int maxit) {
   if (!P->r) {
     double **vecs[] = {&P->r, &P->rh, &P->p, &P->v, &P->s, &P->t, &P->ph, &P->z, &P->y};
-    for (double **q : vecs) HIP_TRY(dalloc(q, (size_t)P->n, P->bytes));
-    HIP_TRY(dalloc(&P->st, 1, P->bytes));
-    HIP_TRY(hipHostMalloc((void **)&P->h_st, sizeof(SolveState), hipHostMallocDefault));
+    for (double **q : vecs) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
+    HIP_TRY(dalloc(&P->st, (size_t)P->count, P->bytes));
+    HIP_TRY(hipHostMalloc((void **)&P->h_st, sizeof(SolveState) * (size_t)P->count, hipHostMallocDefault));
   }
   if (P->hist_cap < maxit + 1) {
     dfree(P->hist);
     P->hist_cap = 0;
-    HIP_TRY(dalloc(&P->hist, 2 * (size_t)(maxit + 1), P->bytes));
+    HIP_TRY(dalloc(&P->hist, (size_t)P->count * 2 * (size_t)(maxit + 1), P->bytes));
     P->hist_cap = maxit + 1;
   }
   return ADR_OK;
@@ -179,9 +222,6 @@ adr_status ensure_iter_buffers(adr_problem *P, int maxit) {
 IterBufs iter_bufs(adr_problem *P, double *x, double tol, int maxit) {
   IterBufs B;
   B.A = P->dia();
-  B.fd = P->fd;
-  B.nx = P->nx;
-  B.ny = P->ny;
   B.b = P->rhs;
   B.x = x;
   B.r = P->r;
@@ -194,8 +234,7 @@ IterBufs iter_bufs(adr_problem *P, double *x, double tol, int maxit) {
   B.z = P->z;
   B.partials = P->partials;
   B.st = P->st;
-  B.hist_l2 = P->hist;
-  B.hist_max = P->hist + P->hist_cap;
+  B.hist = P->hist;
   B.tol = tol;
   B.maxit = maxit;
   return B;
@@ -204,20 +243,19 @@ IterBufs iter_bufs(adr_problem *P, double *x, double tol, int maxit) {
 Factors64 f64_of(const adr_problem *P) { return Factors64{P->lw, P->ls, P->invd}; }
 Factors32 f32_of(const adr_problem *P) { return Factors32{P->lw32, P->ls32, P->invd32, P->E32, P->N32}; }
 
-// One BiCGSTAB pass (13 kernels).
+// One BiCGSTAB pass over the batch (13 kernels).
 hipError_t enqueue_pass(adr_problem *P, const IterBufs &B, hipStream_t s) {
-  const int rows = P->sweep_rows();
-  const int32_t *phase = &P->st->phase;
+  const BatchGeom g = P->geom();
   hipError_t e;
-  if ((e = launch_pass_p(B, P->geom, s)) != hipSuccess) return e;
-  if ((e = launch_lsweep(P->nx, P->ny, rows, P->precision, f64_of(P), f32_of(P), P->p, P->y, P->sync(), phase, s)) != hipSuccess) return e;
-  if ((e = launch_usweep(P->nx, P->ny, rows, P->precision, P->dia(), f64_of(P), f32_of(P), P->y, P->ph, P->sync(), phase, s)) != hipSuccess) return e;
-  if ((e = launch_pass_v(B, P->geom, s)) != hipSuccess) return e;
-  if ((e = launch_pass_s(B, P->geom, s)) != hipSuccess) return e;
-  if ((e = launch_lsweep(P->nx, P->ny, rows, P->precision, f64_of(P), f32_of(P), P->s, P->y, P->sync(), phase, s)) != hipSuccess) return e;
-  if ((e = launch_usweep(P->nx, P->ny, rows, P->precision, P->dia(), f64_of(P), f32_of(P), P->y, P->z, P->sync(), phase, s)) != hipSuccess) return e;
-  if ((e = launch_pass_t(B, P->geom, s)) != hipSuccess) return e;
-  return launch_pass_xr(B, P->geom, s);
+  if ((e = launch_pass_p(B, g, s)) != hipSuccess) return e;
+  if ((e = launch_lsweep(g, P->precision, f64_of(P), f32_of(P), P->p, P->y, P->sync(), P->st, s)) != hipSuccess) return e;
+  if ((e = launch_usweep(g, P->precision, P->dia(), f64_of(P), f32_of(P), P->y, P->ph, P->sync(), P->st, s)) != hipSuccess) return e;
+  if ((e = launch_pass_v(B, g, s)) != hipSuccess) return e;
+  if ((e = launch_pass_s(B, g, s)) != hipSuccess) return e;
+  if ((e = launch_lsweep(g, P->precision, f64_of(P), f32_of(P), P->s, P->y, P->sync(), P->st, s)) != hipSuccess) return e;
+  if ((e = launch_usweep(g, P->precision, P->dia(), f64_of(P), f32_of(P), P->y, P->z, P->sync(), P->st, s)) != hipSuccess) return e;
+  if ((e = launch_pass_t(B, g, s)) != hipSuccess) return e;
+  return launch_pass_xr(B, g, s);
 }
 
 adr_status build_graph(adr_problem *P, const IterBufs &B, int K) {
@@ -240,6 +278,76 @@ adr_status build_graph(adr_problem *P, const IterBufs &B, int K) {
   (void)hipGraphDestroy(g);
   HIP_TRY(e3);
   P->g_K = K;
+  return ADR_OK;
+}
+
+adr_status set_rows(adr_problem *P, int R) {
+  if (R == P->rows) return ADR_OK;
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return build_table(P, R);
+}
+
+// Assemble instance k into its slices of the batched arrays.
+adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double amp) {
+  const Inst &I = P->inst[k];
+  const int nx = I.nx, ny = I.ny;
+  const double eps = P->eps[k], X = P->X[k], Y = P->Y[k];
+  const double dx = X / (double)(nx + 1), dy = Y / (double)(ny + 1);
+  const double e1 = std::exp(-1.0);
+  std::vector<double> tx(6 * (size_t)nx), ty(7 * (size_t)ny);
+  double *xi = &tx[0], *ai = xi + nx, *exi = ai + nx, *uy0 = exi + nx, *uyY = uy0 + nx, *gyY = uyY + nx;
+  double *yj = &ty[0], *bj = yj + ny, *eyj = bj + ny, *ebj = eyj + ny, *ux0 = ebj + ny, *uxX = ux0 + ny,
+         *gxX = uxX + ny;
+  // 1-D tables on the host (the same formulas and libm as the CPU reference)
+  for (int i = 0; i < nx; ++i) {
+    const double x = (double)(i + 1) * dx;
+    xi[i] = x;
+    ai[i] = 1.0 + x * x;
+    exi[i] = std::exp(-x / X);
+    uy0[i] = 0.0;
+    uyY[i] = (exi[i] * (1.0 - e1)) * Y;
+    gyY[i] = exi[i] * (e1 + (1.0 - e1));
+  }
+  for (int j = 0; j < ny; ++j) {
+    const double y = (double)(j + 1) * dy;
+    yj[j] = y;
+    ebj[j] = std::exp(-y);
+    bj[j] = X * std::exp(-y);
+    eyj[j] = std::exp(-y / Y);
+    ux0[j] = (1.0 - eyj[j]) * y;
+    uxX[j] = (e1 * (1.0 - eyj[j])) * y;
+    gxX[j] = (((-1.0 / X) * e1) * (1.0 - eyj[j])) * y;
+  }
+  double *dtab = nullptr;
+  size_t tb = 0;
+  HIP_TRY(dalloc(&dtab, tx.size() + ty.size(), tb));
+  hipError_t e = hipMemcpyAsync(dtab, tx.data(), tx.size() * sizeof(double), hipMemcpyHostToDevice, P->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dtab + tx.size(), ty.data(), ty.size() * sizeof(double), hipMemcpyHostToDevice, P->stream);
+  AssembleArgs a;
+  a.nx = nx; a.ny = ny; a.scheme = P->scheme[k]; a.bc = P->bc[k];
+  a.eps = eps; a.X = X; a.Y = Y; a.dx = dx; a.dy = dy;
+  const double *dx0 = dtab, *dy0 = dtab + tx.size();
+  a.xi = dx0; a.ai = dx0 + nx; a.exi = dx0 + 2 * nx; a.uy0 = dx0 + 3 * nx; a.uyY = dx0 + 4 * nx; a.gyY = dx0 + 5 * nx;
+  a.yj = dy0; a.bj = dy0 + ny; a.eyj = dy0 + 2 * ny; a.ebj = dy0 + 3 * ny; a.ux0 = dy0 + 4 * ny; a.uxX = dy0 + 5 * ny;
+  a.gxX = dy0 + 6 * ny;
+  a.field = field_dev ? field_dev + I.off : nullptr;
+  a.amp = amp;
+  a.S = P->S + I.off; a.W = P->W + I.off; a.C = P->C + I.off; a.E = P->E + I.off; a.N = P->N + I.off;
+  a.rhs = P->rhs + I.off;
+  a.partials = P->partials;
+  a.fmax = P->scal;
+  if (e == hipSuccess) e = launch_assemble(a, make_geom(I.n), P->stream);
+  hipError_t es = hipStreamSynchronize(P->stream);
+  (void)hipFree(dtab);
+  HIP_TRY(e);
+  HIP_TRY(es);
+  return ADR_OK;
+}
+
+adr_status require_single(const adr_problem *P) {
+  if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
+  if (P->count != 1) return fail(ADR_ERR_STATE, "this call needs a single-instance problem");
   return ADR_OK;
 }
 
@@ -281,101 +389,86 @@ void adr_destroy(adr_problem *P) {
   dfree(P->ticket);
   dfree(P->handoff);
   dfree(P->err);
+  dfree(P->d_inst);
   if (P->h_st) (void)hipHostFree(P->h_st);
   delete P;
+}
+
+adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X, const double *Y,
+                              const int32_t *nx, const int32_t *ny, const int32_t *scheme,
+                              const int32_t *bc, const double *field_dev, double amp, void *stream,
+                              adr_problem **out) {
+  g_last_error.clear();
+  if (!out) return fail(ADR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (count < 1) return fail(ADR_ERR_ARG, "count must be >= 1 (got %d)", count);
+  if (!eps || !X || !Y || !nx || !ny || !scheme || !bc) return fail(ADR_ERR_ARG, "NULL parameter array");
+  int64_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    if (!(eps[k] > 0.0) || !std::isfinite(eps[k]))
+      return fail(ADR_ERR_ARG, "instance %d: eps must be a finite number > 0 (got %g)", k, eps[k]);
+    if (!(X[k] > 0.0) || !(Y[k] > 0.0) || !std::isfinite(X[k]) || !std::isfinite(Y[k]))
+      return fail(ADR_ERR_ARG, "instance %d: X and Y must be finite and > 0 (got %g, %g)", k, X[k], Y[k]);
+    if (nx[k] < 1 || ny[k] < 1)
+      return fail(ADR_ERR_ARG, "instance %d: nx and ny must be >= 1 (got %d, %d)", k, nx[k], ny[k]);
+    if (scheme[k] != ADR_UPWIND && scheme[k] != ADR_CENTERED)
+      return fail(ADR_ERR_ARG, "instance %d: unknown scheme %d", k, scheme[k]);
+    if (bc[k] != ADR_BC_DIRICHLET && bc[k] != ADR_BC_NEUMANN_XY)
+      return fail(ADR_ERR_ARG, "instance %d: unknown bc %d", k, bc[k]);
+    if ((int64_t)nx[k] * ny[k] > (int64_t)0x7fffffff)
+      return fail(ADR_ERR_ARG, "instance %d: nx*ny must be < 2^31", k);
+    total += (int64_t)nx[k] * ny[k];
+  }
+  if (field_dev && !std::isfinite(amp)) return fail(ADR_ERR_ARG, "amp must be finite");
+
+  adr_problem *P = new adr_problem();
+  auto bail = [&](adr_status st) {
+    adr_destroy(P);
+    return st;
+  };
+  if (hipGetDevice(&P->dev) != hipSuccess) return bail(fail(ADR_ERR_DEVICE, "no HIP device"));
+  P->stream = (hipStream_t)stream;
+  P->count = count;
+  P->eps.assign(eps, eps + count);
+  P->X.assign(X, X + count);
+  P->Y.assign(Y, Y + count);
+  P->nx.assign(nx, nx + count);
+  P->ny.assign(ny, ny + count);
+  P->scheme.assign(scheme, scheme + count);
+  P->bc.assign(bc, bc + count);
+  P->inst.resize(count);
+  P->max_ny = *std::max_element(ny, ny + count);
+  adr_status st = build_table(P, default_rows(P->max_ny));
+  if (st != ADR_OK) return bail(st);
+  double **arrs[] = {&P->S, &P->W, &P->C, &P->E, &P->N, &P->rhs};
+  for (double **q : arrs)
+    if (dalloc(q, (size_t)P->ntot, P->bytes) != hipSuccess) return bail(fail(ADR_ERR_NOMEM, "device allocation failed"));
+  // partials: 4 slots for every streaming block of the batch, and of one instance's assembly
+  if (dalloc(&P->partials, (size_t)4 * P->nblk + 4 * 2048, P->bytes) != hipSuccess ||
+      dalloc(&P->scal, 8, P->bytes) != hipSuccess || dalloc(&P->bad, (size_t)count, P->bytes) != hipSuccess)
+    return bail(fail(ADR_ERR_NOMEM, "device allocation failed"));
+  for (int k = 0; k < count; ++k) {
+    st = assemble_one(P, k, field_dev, amp);
+    if (st != ADR_OK) return bail(st);
+  }
+  *out = P;
+  return ADR_OK;
 }
 
 adr_status adr_assemble(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme,
                         int32_t bc, const double *field_dev, double amp, void *stream,
                         adr_problem **out) {
+  return adr_batch_assemble(1, &eps, &X, &Y, &nx, &ny, &scheme, &bc, field_dev, amp, stream, out);
+}
+
+adr_status adr_batch_layout(const adr_problem *P, int32_t *count, int64_t *offsets) {
   g_last_error.clear();
-  if (!out) return fail(ADR_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ADR_ERR_ARG, "eps must be a finite number > 0 (got %g)", eps);
-  if (!(X > 0.0) || !(Y > 0.0) || !std::isfinite(X) || !std::isfinite(Y))
-    return fail(ADR_ERR_ARG, "X and Y must be finite and > 0 (got %g, %g)", X, Y);
-  if (nx < 1 || ny < 1) return fail(ADR_ERR_ARG, "nx and ny must be >= 1 (got %d, %d)", nx, ny);
-  if ((int64_t)nx * (int64_t)ny > (int64_t)0x7fffffff) return fail(ADR_ERR_ARG, "nx*ny must be < 2^31");
-  if (scheme != ADR_UPWIND && scheme != ADR_CENTERED) return fail(ADR_ERR_ARG, "unknown scheme %d", scheme);
-  if (bc != ADR_BC_DIRICHLET && bc != ADR_BC_NEUMANN_XY) return fail(ADR_ERR_ARG, "unknown bc %d", bc);
-  if (field_dev && !std::isfinite(amp)) return fail(ADR_ERR_ARG, "amp must be finite");
-
-  adr_problem *P = new adr_problem();
-  HIP_TRY(hipGetDevice(&P->dev));
-  P->stream = (hipStream_t)stream;
-  P->eps = eps; P->X = X; P->Y = Y; P->nx = nx; P->ny = ny; P->scheme = scheme; P->bc = bc;
-  P->n = (int64_t)nx * ny;
-  P->geom = make_geom(P->n);
-  P->fd = make_fastdiv((uint32_t)nx);
-
-  auto cleanup_fail = [&](adr_status st) { adr_destroy(P); return st; };
-#define TRY_P(expr)                                              \
-  do {                                                           \
-    hipError_t e_ = (expr);                                      \
-    if (e_ != hipSuccess) {                                      \
-      (void)hipGetLastError();                                   \
-      adr_status st_ = fail(e_ == hipErrorOutOfMemory ? ADR_ERR_NOMEM : ADR_ERR_DEVICE, \
-                            "%s: %s", #expr, hipGetErrorString(e_)); \
-      return cleanup_fail(st_);                                  \
-    }                                                            \
-  } while (0)
-
-  double **arrs[] = {&P->S, &P->W, &P->C, &P->E, &P->N, &P->rhs};
-  for (double **q : arrs) TRY_P(dalloc(q, (size_t)P->n, P->bytes));
-  TRY_P(dalloc(&P->partials, (size_t)4 * P->geom.nblk, P->bytes));
-  TRY_P(dalloc(&P->scal, 8, P->bytes));
-  TRY_P(dalloc(&P->bad, 1, P->bytes));
-
-  // 1-D tables on the host (same formulas and libm as the CPU reference)
-  const double dx = X / (double)(nx + 1), dy = Y / (double)(ny + 1);
-  const double e1 = std::exp(-1.0);
-  std::vector<double> tx(6 * (size_t)nx), ty(7 * (size_t)ny);
-  double *xi = &tx[0], *ai = xi + nx, *exi = ai + nx, *uy0 = exi + nx, *uyY = uy0 + nx, *gyY = uyY + nx;
-  double *yj = &ty[0], *bj = yj + ny, *eyj = bj + ny, *ebj = eyj + ny, *ux0 = ebj + ny, *uxX = ux0 + ny,
-         *gxX = uxX + ny;
-  for (int i = 0; i < nx; ++i) {
-    const double x = (double)(i + 1) * dx;
-    xi[i] = x;
-    ai[i] = 1.0 + x * x;
-    exi[i] = std::exp(-x / X);
-    uy0[i] = 0.0;
-    uyY[i] = (exi[i] * (1.0 - e1)) * Y;
-    gyY[i] = exi[i] * (e1 + (1.0 - e1));
+  if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
+  if (count) *count = P->count;
+  if (offsets) {
+    for (int k = 0; k < P->count; ++k) offsets[k] = P->inst[k].off;
+    offsets[P->count] = P->ntot;
   }
-  for (int j = 0; j < ny; ++j) {
-    const double y = (double)(j + 1) * dy;
-    yj[j] = y;
-    ebj[j] = std::exp(-y);
-    bj[j] = X * std::exp(-y);
-    eyj[j] = std::exp(-y / Y);
-    ux0[j] = (1.0 - eyj[j]) * y;
-    uxX[j] = (e1 * (1.0 - eyj[j])) * y;
-    gxX[j] = (((-1.0 / X) * e1) * (1.0 - eyj[j])) * y;
-  }
-  double *dtab = nullptr;
-  size_t tb = 0;
-  TRY_P(dalloc(&dtab, tx.size() + ty.size(), tb));
-  TRY_P(hipMemcpyAsync(dtab, tx.data(), tx.size() * sizeof(double), hipMemcpyHostToDevice, P->stream));
-  TRY_P(hipMemcpyAsync(dtab + tx.size(), ty.data(), ty.size() * sizeof(double), hipMemcpyHostToDevice, P->stream));
-  AssembleArgs a;
-  a.nx = nx; a.ny = ny; a.scheme = scheme; a.bc = bc;
-  a.eps = eps; a.X = X; a.Y = Y; a.dx = dx; a.dy = dy;
-  const double *dx0 = dtab, *dy0 = dtab + tx.size();
-  a.xi = dx0; a.ai = dx0 + nx; a.exi = dx0 + 2 * nx; a.uy0 = dx0 + 3 * nx; a.uyY = dx0 + 4 * nx; a.gyY = dx0 + 5 * nx;
-  a.yj = dy0; a.bj = dy0 + ny; a.eyj = dy0 + 2 * ny; a.ebj = dy0 + 3 * ny; a.ux0 = dy0 + 4 * ny; a.uxX = dy0 + 5 * ny;
-  a.gxX = dy0 + 6 * ny;
-  a.field = field_dev;
-  a.amp = amp;
-  a.S = P->S; a.W = P->W; a.C = P->C; a.E = P->E; a.N = P->N; a.rhs = P->rhs;
-  a.partials = P->partials;
-  a.fmax = P->scal;
-  hipError_t ea = launch_assemble(a, P->geom, P->stream);
-  hipError_t es = hipStreamSynchronize(P->stream);
-  (void)hipFree(dtab);
-  TRY_P(ea);
-  TRY_P(es);
-#undef TRY_P
-  *out = P;
   return ADR_OK;
 }
 
@@ -386,7 +479,8 @@ adr_status adr_get_dia(const adr_problem *P, double *S, double *W, double *C, do
   const double *src[] = {P->S, P->W, P->C, P->E, P->N, P->rhs};
   double *dst[] = {S, W, C, E, N, rhs};
   for (int q = 0; q < 6; ++q)
-    if (dst[q]) HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)P->n * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    if (dst[q])
+      HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)P->ntot * sizeof(double), hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   return ADR_OK;
 }
@@ -400,7 +494,7 @@ adr_status adr_set_dia(adr_problem *P, const double *S, const double *W, const d
   for (int q = 0; q < 6; ++q)
     if (!src[q]) return fail(ADR_ERR_ARG, "all six arrays are required");
   for (int q = 0; q < 6; ++q)
-    HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)P->n * sizeof(double), hipMemcpyHostToDevice, P->stream));
+    HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)P->ntot * sizeof(double), hipMemcpyHostToDevice, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   P->factored = 0;
   return ADR_OK;
@@ -413,7 +507,8 @@ adr_status adr_get_factors(const adr_problem *P, double *lw, double *ls, double 
   const double *src[] = {P->lw, P->ls, P->invd};
   double *dst[] = {lw, ls, invd};
   for (int q = 0; q < 3; ++q)
-    if (dst[q]) HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)P->n * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    if (dst[q])
+      HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)P->ntot * sizeof(double), hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   return ADR_OK;
 }
@@ -421,54 +516,85 @@ adr_status adr_get_factors(const adr_problem *P, double *lw, double *ls, double 
 adr_status adr_set_sweep_rows(adr_problem *P, int32_t rows) {
   g_last_error.clear();
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
-  if (rows != 0 && rows != 15 && rows != 31)
-    return fail(ADR_ERR_ARG, "rows must be 0, 15 or 31 (got %d)", rows);
-  P->rows = rows;
-  return ADR_OK;
+  if (rows != 0 && rows != 15 && rows != 31) return fail(ADR_ERR_ARG, "rows must be 0, 15 or 31 (got %d)", rows);
+  return set_rows(P, rows ? rows : default_rows(P->max_ny));
 }
 
 size_t adr_device_bytes(const adr_problem *P) { return P ? P->bytes : 0; }
 
-adr_status adr_ilu0(adr_problem *P, int32_t precision, int64_t *bad_index) {
+adr_status adr_batch_ilu0(adr_problem *P, int32_t precision, int64_t *bad_index) {
   g_last_error.clear();
-  if (bad_index) *bad_index = -1;
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
+  if (bad_index)
+    for (int k = 0; k < P->count; ++k) bad_index[k] = -1;
   if (precision < ADR_FP64 || precision > ADR_FP32_SWEEPS) return fail(ADR_ERR_ARG, "unknown precision %d", precision);
   adr_status st = ensure_sync(P);
   if (st != ADR_OK) return st;
   if (!P->lw) {
-    HIP_TRY(dalloc(&P->lw, (size_t)P->n, P->bytes));
-    HIP_TRY(dalloc(&P->ls, (size_t)P->n, P->bytes));
-    HIP_TRY(dalloc(&P->invd, (size_t)P->n, P->bytes));
+    HIP_TRY(dalloc(&P->lw, (size_t)P->ntot, P->bytes));
+    HIP_TRY(dalloc(&P->ls, (size_t)P->ntot, P->bytes));
+    HIP_TRY(dalloc(&P->invd, (size_t)P->ntot, P->bytes));
   }
   if (precision != ADR_FP64 && !P->lw32) {
     float **fv[] = {&P->lw32, &P->ls32, &P->invd32, &P->E32, &P->N32};
-    for (float **q : fv) HIP_TRY(dalloc(q, (size_t)P->n, P->bytes));
+    for (float **q : fv) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
   }
   P->factored = 0;
-  HIP_TRY(launch_fill_u64((uint64_t *)P->bad, 1, ~0ull, P->stream));
+  HIP_TRY(launch_fill_u64((uint64_t *)P->bad, P->count, ~0ull, P->stream));
   Factors32 h{};
   if (precision != ADR_FP64) h = f32_of(P);
-  HIP_TRY(launch_ilu0(P->dia(), P->nx, P->ny, P->sweep_rows(), f64_of(P), h, P->sync(), P->bad, P->stream));
-  uint64_t hb = 0;
-  HIP_TRY(hipMemcpyAsync(&hb, P->bad, sizeof(hb), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(launch_ilu0(P->dia(), P->geom(), f64_of(P), h, P->sync(), P->bad, P->stream));
+  std::vector<uint64_t> hb((size_t)P->count);
+  HIP_TRY(hipMemcpyAsync(hb.data(), P->bad, sizeof(uint64_t) * hb.size(), hipMemcpyDeviceToHost, P->stream));
   st = check_device_fault(P);
   if (st != ADR_OK) return st;
-  if (hb != ~0ull) {
-    if (bad_index) *bad_index = (int64_t)hb;
-    return fail(ADR_ZERO_PIVOT, "zero or non-finite pivot at unknown %lld", (long long)hb);
-  }
+  int first_bad = -1;
+  for (int k = 0; k < P->count; ++k)
+    if (hb[k] != ~0ull) {
+      if (bad_index) bad_index[k] = (int64_t)hb[k];
+      if (first_bad < 0) first_bad = k;
+    }
+  if (first_bad >= 0)
+    return fail(ADR_ZERO_PIVOT, "instance %d: zero or non-finite pivot at unknown %lld", first_bad,
+                (long long)hb[first_bad]);
   P->factored = 1;
   P->precision = precision;
   return ADR_OK;
 }
 
+adr_status adr_ilu0(adr_problem *P, int32_t precision, int64_t *bad_index) {
+  g_last_error.clear();
+  adr_status st = require_single(P);
+  if (st != ADR_OK) return st;
+  return adr_batch_ilu0(P, precision, bad_index);
+}
+
 adr_status adr_spmv(adr_problem *P, const double *x, double *v) {
   g_last_error.clear();
-  if (!P || !x || !v) return fail(ADR_ERR_ARG, "NULL argument");
-  HIP_TRY(launch_spmv(P->dia(), P->fd, P->nx, P->ny, x, v, P->geom, P->stream));
+  adr_status st = require_single(P);
+  if (st != ADR_OK) return st;
+  if (!x || !v) return fail(ADR_ERR_ARG, "NULL argument");
+  const Inst &I = P->inst[0];
+  HIP_TRY(launch_spmv(P->dia(), I.fd, I.nx, I.ny, x, v, make_geom(I.n), P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   return ADR_OK;
+}
+
+adr_status adr_lsolve(adr_problem *P, const double *q, double *y) {
+  g_last_error.clear();
+  if (!P || !q || !y) return fail(ADR_ERR_ARG, "NULL argument");
+  if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
+  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), q, y, P->sync(), nullptr, P->stream));
+  return check_device_fault(P);
+}
+
+adr_status adr_usolve(adr_problem *P, const double *y, double *z) {
+  g_last_error.clear();
+  if (!P || !y || !z) return fail(ADR_ERR_ARG, "NULL argument");
+  if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
+  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), y, z, P->sync(), nullptr,
+                        P->stream));
+  return check_device_fault(P);
 }
 
 adr_status adr_precond(adr_problem *P, const double *q, double *z) {
@@ -477,26 +603,55 @@ adr_status adr_precond(adr_problem *P, const double *q, double *z) {
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
   adr_status st = ensure_iter_buffers(P, 0);
   if (st != ADR_OK) return st;
-  const int rows = P->sweep_rows();
-  HIP_TRY(launch_lsweep(P->nx, P->ny, rows, P->precision, f64_of(P), f32_of(P), q, P->y, P->sync(), nullptr, P->stream));
-  HIP_TRY(launch_usweep(P->nx, P->ny, rows, P->precision, P->dia(), f64_of(P), f32_of(P), P->y, z, P->sync(), nullptr, P->stream));
+  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), q, P->y, P->sync(), nullptr, P->stream));
+  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->y, z, P->sync(), nullptr,
+                        P->stream));
   return check_device_fault(P);
 }
 
-adr_status adr_lsolve(adr_problem *P, const double *q, double *y) {
+adr_status adr_autotune(adr_problem *P, int32_t *rows_chosen, double *ms_per_apply) {
   g_last_error.clear();
-  if (!P || !q || !y) return fail(ADR_ERR_ARG, "NULL argument");
+  if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
-  HIP_TRY(launch_lsweep(P->nx, P->ny, P->sweep_rows(), P->precision, f64_of(P), f32_of(P), q, y, P->sync(), nullptr, P->stream));
-  return check_device_fault(P);
-}
-
-adr_status adr_usolve(adr_problem *P, const double *y, double *z) {
-  g_last_error.clear();
-  if (!P || !y || !z) return fail(ADR_ERR_ARG, "NULL argument");
-  if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
-  HIP_TRY(launch_usweep(P->nx, P->ny, P->sweep_rows(), P->precision, P->dia(), f64_of(P), f32_of(P), y, z, P->sync(), nullptr, P->stream));
-  return check_device_fault(P);
+  adr_status st = ensure_iter_buffers(P, 0);
+  if (st != ADR_OK) return st;
+  // time M^{-1} applied to the batch's right-hand sides for every strip height
+  const int cand[] = {15, 31};
+  int best = P->rows;
+  float best_ms = -1.f;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  for (int R : cand) {
+    st = set_rows(P, R);
+    if (st != ADR_OK) return st;
+    float ms = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIP_TRY(hipEventRecord(e0, P->stream));
+      HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->rhs, P->y, P->sync(), nullptr,
+                            P->stream));
+      HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->y, P->z, P->sync(), nullptr,
+                            P->stream));
+      HIP_TRY(hipEventRecord(e1, P->stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      float m = 0.f;
+      HIP_TRY(hipEventElapsedTime(&m, e0, e1));
+      if (rep > 0) ms += m / 2.f;   // the first application is a warm-up
+    }
+    st = check_device_fault(P);
+    if (st != ADR_OK) return st;
+    if (best_ms < 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = R;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  st = set_rows(P, best);
+  if (st != ADR_OK) return st;
+  if (rows_chosen) *rows_chosen = best;
+  if (ms_per_apply) *ms_per_apply = best_ms;
+  return ADR_OK;
 }
 
 adr_status adr_dot(const double *x, const double *y, int64_t n, void *stream, double *out) {
@@ -522,11 +677,11 @@ adr_status adr_dot(const double *x, const double *y, int64_t n, void *stream, do
   return ADR_OK;
 }
 
-adr_status adr_bicgstab_solve(adr_problem *P, double tol, int32_t maxit, const double *x0,
-                              double *x, double *hist_l2, double *hist_max, adr_solve_info *info) {
+adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const double *x0, double *x,
+                           double *hist_l2, double *hist_max, adr_solve_info *info) {
   g_last_error.clear();
-  if (info) memset(info, 0, sizeof(*info));
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
+  if (info) memset(info, 0, sizeof(*info) * (size_t)P->count);
   if (!x) return fail(ADR_ERR_ARG, "x_dev is NULL");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(ADR_ERR_ARG, "tol must be finite and >= 0 (got %g)", tol);
   if (maxit < 0) return fail(ADR_ERR_ARG, "maxit must be >= 0 (got %d)", maxit);
@@ -535,27 +690,38 @@ adr_status adr_bicgstab_solve(adr_problem *P, double tol, int32_t maxit, const d
   if (st != ADR_OK) return st;
   st = ensure_sync(P);
   if (st != ADR_OK) return st;
-  const size_t vb = (size_t)P->n * sizeof(double);
+  const BatchGeom g = P->geom();
+  const size_t vb = (size_t)P->ntot * sizeof(double);
   if (x0) {
     if (x0 != x) HIP_TRY(hipMemcpyAsync(x, x0, vb, hipMemcpyDeviceToDevice, P->stream));
   } else {
-    HIP_TRY(launch_fill(x, P->n, 0.0, P->stream));
+    HIP_TRY(launch_fill(x, P->ntot, 0.0, P->stream));
   }
   IterBufs B = iter_bufs(P, x, tol, maxit);
   // passes per graph replay: enough to amortise the host check
-  int K = P->n >= (1 << 22) ? 4 : (P->n >= (1 << 18) ? 8 : 16);
+  int K = P->ntot >= (1 << 22) ? 4 : (P->ntot >= (1 << 18) ? 8 : 16);
   if (K > maxit && maxit > 0) K = maxit;
   if (!P->gexec || P->g_x != x || P->g_tol != tol || P->g_maxit != maxit || P->g_prec != P->precision ||
-      P->g_rows != P->sweep_rows() || P->g_K != K) {
+      P->g_rows != P->rows || P->g_K != K) {
     st = build_graph(P, B, K);
     if (st != ADR_OK) return st;
-    P->g_x = x; P->g_tol = tol; P->g_maxit = maxit; P->g_prec = P->precision; P->g_rows = P->sweep_rows();
+    P->g_x = x;
+    P->g_tol = tol;
+    P->g_maxit = maxit;
+    P->g_prec = P->precision;
+    P->g_rows = P->rows;
   }
+  auto all_done = [&]() {
+    for (int k = 0; k < P->count; ++k)
+      if (P->h_st[k].phase != DONE) return false;
+    return true;
+  };
+  const size_t stb = sizeof(SolveState) * (size_t)P->count;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, P->stream));
-  HIP_TRY(launch_init(B, P->geom, P->stream));
+  HIP_TRY(launch_init(B, g, P->stream));
   // replay chunks; keep one chunk queued behind the one being checked
   const int max_chunks = maxit > 0 ? (maxit + K - 1) / K : 0;
   int launched = 0;
@@ -565,7 +731,7 @@ adr_status adr_bicgstab_solve(adr_problem *P, double tol, int32_t maxit, const d
     ++launched;
   }
   while (!done && launched > 0) {
-    HIP_TRY(hipMemcpyAsync(P->h_st, P->st, sizeof(SolveState), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipMemcpyAsync(P->h_st, P->st, stb, hipMemcpyDeviceToHost, P->stream));
     hipEvent_t ev;
     HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(ev, P->stream));
@@ -575,19 +741,17 @@ adr_status adr_bicgstab_solve(adr_problem *P, double tol, int32_t maxit, const d
     }
     HIP_TRY(hipEventSynchronize(ev));
     (void)hipEventDestroy(ev);
-    if (P->h_st->phase == DONE) done = true;
-    else if (launched >= max_chunks) {
+    if (all_done()) {
+      done = true;
+    } else if (launched >= max_chunks) {
       // the last chunk is queued; wait for it
-      HIP_TRY(hipMemcpyAsync(P->h_st, P->st, sizeof(SolveState), hipMemcpyDeviceToHost, P->stream));
       HIP_TRY(hipStreamSynchronize(P->stream));
       done = true;
     }
   }
   HIP_TRY(hipEventRecord(e1, P->stream));
-  HIP_TRY(launch_true_residual(B, P->geom, P->scal + 1, P->stream));
-  double tres = 0.0;
-  HIP_TRY(hipMemcpyAsync(&tres, P->scal + 1, sizeof(double), hipMemcpyDeviceToHost, P->stream));
-  HIP_TRY(hipMemcpyAsync(P->h_st, P->st, sizeof(SolveState), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(launch_true_residual(B, g, P->stream));
+  HIP_TRY(hipMemcpyAsync(P->h_st, P->st, stb, hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -595,22 +759,40 @@ adr_status adr_bicgstab_solve(adr_problem *P, double tol, int32_t maxit, const d
   (void)hipEventDestroy(e1);
   st = check_device_fault(P);
   if (st != ADR_OK) return st;
-  const SolveState &S = *P->h_st;
-  if (S.phase != DONE) return fail(ADR_ERR_DEVICE, "solve did not reach a stopping state");
-  const int hl = S.hist_len;
-  if (hist_l2 && hl > 0) HIP_TRY(hipMemcpy(hist_l2, P->hist, (size_t)hl * sizeof(double), hipMemcpyDeviceToHost));
-  if (hist_max && hl > 0)
-    HIP_TRY(hipMemcpy(hist_max, P->hist + P->hist_cap, (size_t)hl * sizeof(double), hipMemcpyDeviceToHost));
-  if (info) {
-    info->status = S.status;
-    info->iters = S.iter;
-    info->hist_len = hl;
-    info->half_step = S.half_step;
-    info->bnorm = S.bnorm;
-    info->true_relres = S.bnorm > 0.0 ? std::sqrt(tres) / S.bnorm : 0.0;
-    info->solve_ms = ms;
+  adr_status result = ADR_OK;
+  for (int k = 0; k < P->count; ++k) {
+    const SolveState &S = P->h_st[k];
+    if (S.phase != DONE) return fail(ADR_ERR_DEVICE, "instance %d did not reach a stopping state", k);
+    const int hl = S.hist_len;
+    const double *hsrc = P->hist + (size_t)k * 2 * (size_t)(maxit + 1);
+    if (hist_l2 && hl > 0)
+      HIP_TRY(hipMemcpy(hist_l2 + (size_t)k * (maxit + 1), hsrc, (size_t)hl * sizeof(double), hipMemcpyDeviceToHost));
+    if (hist_max && hl > 0)
+      HIP_TRY(hipMemcpy(hist_max + (size_t)k * (maxit + 1), hsrc + (maxit + 1), (size_t)hl * sizeof(double),
+                        hipMemcpyDeviceToHost));
+    if (info) {
+      info[k].status = S.status;
+      info[k].iters = S.iter;
+      info[k].hist_len = hl;
+      info[k].half_step = S.half_step;
+      info[k].bnorm = S.bnorm;
+      info[k].true_relres = S.bnorm > 0.0 ? std::sqrt(S.true_res2) / S.bnorm : 0.0;
+      info[k].solve_ms = ms;
+    }
+    if (result == ADR_OK && S.status != ADR_OK) result = (adr_status)S.status;
   }
-  return (adr_status)S.status;
+  return result;
+}
+
+adr_status adr_bicgstab_solve(adr_problem *P, double tol, int32_t maxit, const double *x0, double *x,
+                              double *hist_l2, double *hist_max, adr_solve_info *info) {
+  g_last_error.clear();
+  adr_status st = require_single(P);
+  if (st != ADR_OK) {
+    if (info) memset(info, 0, sizeof(*info));
+    return st;
+  }
+  return adr_batch_solve(P, tol, maxit, x0, x, hist_l2, hist_max, info);
 }
 
 }  // extern "C"

@@ -1,5 +1,11 @@
 // Internal declarations shared by the library's kernel and host sources.
 // Not part of the public ABI (see include/adr.h).
+//
+// Every iteration kernel works on a batch of independent instances (a single
+// problem is a batch of one).  Instance k owns the slice [off, off + n) of
+// each batched vector, the block range [blk0, blk0 + nblk) of the streaming
+// kernels and the strip range [strip0, strip0 + nstrips) of the wavefront
+// kernels; kernels find their instance by binary search over those starts.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,7 +22,7 @@ enum Phase : int32_t { RUNNING = 0, HALF_STEP = 1, DONE = 2 };
 
 struct SolveState {
   double rho, rho_prev, alpha, omega, beta;
-  double bnorm, thr;
+  double bnorm, thr, true_res2;
   int32_t iter;       // index of the pass in progress (passes started)
   int32_t status;     // adr_status once phase == DONE
   int32_t phase;      // Phase
@@ -27,7 +33,7 @@ struct SolveState {
   int32_t pad;
 };
 
-// Five diagonals (lexicographic order, x fastest).
+// Five diagonals (lexicographic order, x fastest), batched base pointers.
 struct Dia {
   const double *S, *W, *C, *E, *N;
 };
@@ -38,19 +44,36 @@ struct FastDiv {
   uint32_t d, m, s;
 };
 
-// Slots of the per-block double-double partial sums.
-enum Slot : int { SLOT_A = 0, SLOT_B = 1, SLOT_C = 2, NSLOT = 3 };
+// One instance of a batch.
+struct Inst {
+  int32_t nx, ny, n;
+  int32_t chunk;            // points per streaming block (multiple of 256)
+  int64_t off;              // offset of the instance in every batched vector
+  int32_t blk0, nblk;       // streaming blocks (blk0 and nblk multiples of 8)
+  int32_t strip0, nstrips;  // wavefront strips (for the batch's strip height)
+  int64_t ho_off;           // offset in the hand-off buffer (64-bit words)
+  FastDiv fd;               // division by nx
+  int32_t pad;
+};
 
-// Launch geometry of the streaming kernels: nblk blocks of 256 threads,
-// each owning `chunk` consecutive points (a multiple of 256).
+// Launch geometry of a batch.
+struct BatchGeom {
+  const Inst *inst;   // device table
+  int ninst;
+  int nblk;           // total streaming blocks
+  int nstrips;        // total strips
+  int rows;           // strip height R
+};
+
+// Single-instance streaming geometry (assembly, diagnostics).
 struct Stream1D {
   int n, nblk, chunk;
 };
 
-// Wavefront sweep geometry and synchronisation memory.
+// Wavefront synchronisation memory.
 struct SweepSync {
   unsigned *ticket;      // [2]: strip ticket, finished-strip counter
-  uint64_t *handoff;     // [nstrips * nx]: last row of each strip, sentinel-filled
+  uint64_t *handoff;     // last row of each strip, sentinel-filled
   int *err;              // device fault report (spin limit exceeded)
 };
 
@@ -81,42 +104,40 @@ hipError_t launch_spmv(const Dia &A, FastDiv fd, int nx, int ny, const double *x
 hipError_t launch_dot(const double *x, const double *y, const Stream1D &g, double2 *partials,
                       double *out, hipStream_t s);
 
-// BiCGSTAB step kernels.
+// BiCGSTAB step kernels (batched).
 struct IterBufs {
   Dia A;
-  FastDiv fd;
-  int nx, ny;
   const double *b;
   double *x, *r, *rh, *p, *v, *s, *t, *ph, *z;
-  double2 *partials;   // [NSLOT][maxblk] plus max slots
-  SolveState *st;
-  double *hist_l2, *hist_max;   // device, maxit+1
+  double2 *partials;   // [4][total blocks]
+  SolveState *st;      // [ninst]
+  double *hist;        // [ninst][2][maxit + 1]
   double tol;
   int maxit;
 };
-hipError_t launch_init(const IterBufs &B, const Stream1D &g, hipStream_t s);
-hipError_t launch_pass_p(const IterBufs &B, const Stream1D &g, hipStream_t s);
-hipError_t launch_pass_v(const IterBufs &B, const Stream1D &g, hipStream_t s);
-hipError_t launch_pass_s(const IterBufs &B, const Stream1D &g, hipStream_t s);
-hipError_t launch_pass_t(const IterBufs &B, const Stream1D &g, hipStream_t s);
-hipError_t launch_pass_xr(const IterBufs &B, const Stream1D &g, hipStream_t s);
-hipError_t launch_true_residual(const IterBufs &B, const Stream1D &g, double *out, hipStream_t s);
+hipError_t launch_init(const IterBufs &B, const BatchGeom &g, hipStream_t s);
+hipError_t launch_pass_p(const IterBufs &B, const BatchGeom &g, hipStream_t s);
+hipError_t launch_pass_v(const IterBufs &B, const BatchGeom &g, hipStream_t s);
+hipError_t launch_pass_s(const IterBufs &B, const BatchGeom &g, hipStream_t s);
+hipError_t launch_pass_t(const IterBufs &B, const BatchGeom &g, hipStream_t s);
+hipError_t launch_pass_xr(const IterBufs &B, const BatchGeom &g, hipStream_t s);
+hipError_t launch_true_residual(const IterBufs &B, const BatchGeom &g, hipStream_t s);
 
-// Wavefront kernels.  rows = strip height R (15, 31 or 63).
+// Wavefront kernels.  rows = strip height R (15 or 31).
 struct Factors64 {
   double *lw, *ls, *invd;
 };
 struct Factors32 {
   float *lw, *ls, *invd, *E, *N;
 };
-hipError_t launch_ilu0(const Dia &A, int nx, int ny, int rows, Factors64 f64, Factors32 f32,
+hipError_t launch_ilu0(const Dia &A, const BatchGeom &g, Factors64 f64, Factors32 f32,
                        const SweepSync &sync, int64_t *bad, hipStream_t s);
 // precision: 0 = FP64 factors, 1 = FP32 factors/FP64 arithmetic, 2 = FP32 arithmetic
-hipError_t launch_lsweep(int nx, int ny, int rows, int precision, const Factors64 &f64,
+hipError_t launch_lsweep(const BatchGeom &g, int precision, const Factors64 &f64,
                          const Factors32 &f32, const double *q, double *y, const SweepSync &sync,
-                         const int32_t *phase, hipStream_t s);
-hipError_t launch_usweep(int nx, int ny, int rows, int precision, const Dia &A,
-                         const Factors64 &f64, const Factors32 &f32, const double *y, double *z,
-                         const SweepSync &sync, const int32_t *phase, hipStream_t s);
+                         const SolveState *st, hipStream_t s);
+hipError_t launch_usweep(const BatchGeom &g, int precision, const Dia &A, const Factors64 &f64,
+                         const Factors32 &f32, const double *y, double *z, const SweepSync &sync,
+                         const SolveState *st, hipStream_t s);
 
 }  // namespace adr

@@ -338,44 +338,79 @@ hipError_t launch_dot(const double *x, const double *y, const Stream1D &g, doubl
 }
 
 // ---------------------------------------------------------------------------
-// BiCGSTAB (Section 5.2): vector kernels and their finalize steps.
+// BiCGSTAB (Section 5.2): vector kernels and their finalize steps, batched:
+// block b of a streaming kernel belongs to the instance whose block range
+// holds b; finalize kernels run one block per instance.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
 
+__device__ __forceinline__ int find_block_inst(const Inst *inst, int ninst, int b) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].blk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Instance, local tile range [beg, end) and the instance's offset for block b.
+#define ADR_BATCH_BLOCK(g)                                                    \
+  const int ii = find_block_inst((g).inst, (g).ninst, (int)blockIdx.x);      \
+  const Inst I = (g).inst[ii];                                               \
+  const int tile_ = xcd_tile((int)blockIdx.x - I.blk0, I.nblk);              \
+  const int beg = tile_ * I.chunk;                                           \
+  const int end = min(beg + I.chunk, I.n);                                   \
+  const int64_t o = I.off
+
+__device__ __forceinline__ double *hist_l2_of(const IterBufs &B, int i) {
+  return B.hist + (size_t)i * 2 * (size_t)(B.maxit + 1);
+}
+__device__ __forceinline__ double *hist_max_of(const IterBufs &B, int i) {
+  return hist_l2_of(B, i) + (B.maxit + 1);
+}
+
 // r = b - A x, r^ = r; partials: b.b (A), r.r (B), max|r|.
-__global__ __launch_bounds__(BLK) void k_init(IterBufs B, Stream1D g) {
-  ADR_BLOCK_RANGE(g, beg, end);
+__global__ __launch_bounds__(BLK) void k_init(IterBufs B, BatchGeom g) {
+  ADR_BATCH_BLOCK(g);
+  Dia A{B.A.S + o, B.A.W + o, B.A.C + o, B.A.E + o, B.A.N + o};
+  const double *bb = B.b + o, *x = B.x + o;
+  double *r = B.r + o, *rh = B.rh + o;
   dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
   double mx = 0.0;
   for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    const int j = (int)fdiv((uint32_t)k, B.fd), i = k - j * B.nx;
-    const double bk = B.b[k];
-    const double rk = bk - spmv_point(B.A, B.x, k, i, j, B.nx, B.ny);
-    B.r[k] = rk;
-    B.rh[k] = rk;
+    const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
+    const double bk = bb[k];
+    const double rk = bk - spmv_point(A, x, k, i, j, I.nx, I.ny);
+    r[k] = rk;
+    rh[k] = rk;
     acc[0] = dd_add(acc[0], dd_prod(bk, bk));
     acc[1] = dd_add(acc[1], dd_prod(rk, rk));
     mx = nanmax(mx, fabs(rk));
   }
   block_partials<2, true>(acc, mx, B.partials, g.nblk, blockIdx.x);
 }
-__global__ __launch_bounds__(BLK) void k_init_fin(IterBufs B, Stream1D g) {
-  const dd bb = combine_dd(B.partials, g.nblk);
-  const dd rr = combine_dd(B.partials + (size_t)g.nblk, g.nblk);
-  const double rmax = combine_max(B.partials + (size_t)3 * g.nblk, g.nblk);
+__global__ __launch_bounds__(BLK) void k_init_fin(IterBufs B, BatchGeom g) {
+  const int ii = blockIdx.x;
+  const Inst I = g.inst[ii];
+  const dd bb = combine_dd(B.partials + I.blk0, I.nblk);
+  const dd rr = combine_dd(B.partials + (size_t)g.nblk + I.blk0, I.nblk);
+  const double rmax = combine_max(B.partials + (size_t)3 * g.nblk + I.blk0, I.nblk);
   if (threadIdx.x != 0) return;
-  SolveState &S = *B.st;
+  SolveState &S = B.st[ii];
+  double *h2 = hist_l2_of(B, ii), *hm = hist_max_of(B, ii);
   S.maxit = B.maxit;
   S.iter = 0;
   S.hist_len = 0;
   S.half_step = 0;
   S.zero_x = 0;
   S.rho = S.rho_prev = S.alpha = S.omega = S.beta = 0.0;
+  S.true_res2 = 0.0;
   const double bnorm = sqrt(bb.hi);
   S.bnorm = bnorm;
   if (bnorm == 0.0) {
-    B.hist_l2[0] = 0.0;
-    B.hist_max[0] = 0.0;
+    h2[0] = 0.0;
+    hm[0] = 0.0;
     S.hist_len = 1;
     S.zero_x = 1;
     S.status = 0;
@@ -384,8 +419,8 @@ __global__ __launch_bounds__(BLK) void k_init_fin(IterBufs B, Stream1D g) {
   }
   S.thr = B.tol * bnorm;
   const double rnorm = sqrt(rr.hi);
-  B.hist_l2[0] = rnorm;
-  B.hist_max[0] = rmax;
+  h2[0] = rnorm;
+  hm[0] = rmax;
   S.hist_len = 1;
   if (!finite(rnorm)) { S.status = 5; S.phase = DONE; return; }
   if (rnorm < S.thr) { S.status = 0; S.phase = DONE; return; }
@@ -397,169 +432,193 @@ __global__ __launch_bounds__(BLK) void k_init_fin(IterBufs B, Stream1D g) {
   S.status = 1;
   S.phase = RUNNING;
 }
-__global__ __launch_bounds__(BLK) void k_zero_x(IterBufs B, Stream1D g) {
-  if (!B.st->zero_x) return;
-  ADR_BLOCK_RANGE(g, beg, end);
-  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) B.x[k] = 0.0;
+__global__ __launch_bounds__(BLK) void k_zero_x(IterBufs B, BatchGeom g) {
+  ADR_BATCH_BLOCK(g);
+  if (!B.st[ii].zero_x) return;
+  double *x = B.x + o;
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) x[k] = 0.0;
 }
-hipError_t launch_init(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+hipError_t launch_init(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(g.nblk), dim3(BLK), 0, s, B, g);
-  hipLaunchKernelGGL(k_init_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_init_fin, dim3(g.ninst), dim3(BLK), 0, s, B, g);
   hipLaunchKernelGGL(k_zero_x, dim3(g.nblk), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }
 
 // p = r (first pass) or p = fma(beta, fma(-omega, v, p), r).
-__global__ __launch_bounds__(BLK) void k_pass_p(IterBufs B, Stream1D g) {
-  if (B.st->phase != RUNNING) return;
-  ADR_BLOCK_RANGE(g, beg, end);
-  if (B.st->iter == 1) {
-    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) B.p[k] = B.r[k];
+__global__ __launch_bounds__(BLK) void k_pass_p(IterBufs B, BatchGeom g) {
+  ADR_BATCH_BLOCK(g);
+  const SolveState &S = B.st[ii];
+  if (S.phase != RUNNING) return;
+  double *p = B.p + o;
+  const double *r = B.r + o, *v = B.v + o;
+  if (S.iter == 1) {
+    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) p[k] = r[k];
   } else {
-    const double beta = B.st->beta, omega = B.st->omega;
-    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) B.p[k] = fma(beta, fma(-omega, B.v[k], B.p[k]), B.r[k]);
+    const double beta = S.beta, omega = S.omega;
+    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) p[k] = fma(beta, fma(-omega, v[k], p[k]), r[k]);
   }
 }
-hipError_t launch_pass_p(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+hipError_t launch_pass_p(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   hipLaunchKernelGGL(k_pass_p, dim3(g.nblk), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }
 
 // v = A p^; partial r^.v; finalize alpha = rho / (r^.v).
-__global__ __launch_bounds__(BLK) void k_pass_v(IterBufs B, Stream1D g) {
-  if (B.st->phase != RUNNING) return;
-  ADR_BLOCK_RANGE(g, beg, end);
+__global__ __launch_bounds__(BLK) void k_pass_v(IterBufs B, BatchGeom g) {
+  ADR_BATCH_BLOCK(g);
+  if (B.st[ii].phase != RUNNING) return;
+  Dia A{B.A.S + o, B.A.W + o, B.A.C + o, B.A.E + o, B.A.N + o};
+  const double *ph = B.ph + o, *rh = B.rh + o;
+  double *v = B.v + o;
   dd acc[1] = {dd{0.0, 0.0}};
   for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    const int j = (int)fdiv((uint32_t)k, B.fd), i = k - j * B.nx;
-    const double vk = spmv_point(B.A, B.ph, k, i, j, B.nx, B.ny);
-    B.v[k] = vk;
-    acc[0] = dd_add(acc[0], dd_prod(B.rh[k], vk));
+    const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
+    const double vk = spmv_point(A, ph, k, i, j, I.nx, I.ny);
+    v[k] = vk;
+    acc[0] = dd_add(acc[0], dd_prod(rh[k], vk));
   }
   block_partials<1, false>(acc, 0.0, B.partials, g.nblk, blockIdx.x);
 }
-__global__ __launch_bounds__(BLK) void k_pass_v_fin(IterBufs B, Stream1D g) {
-  if (B.st->phase != RUNNING) return;
-  const dd rv = combine_dd(B.partials, g.nblk);
+__global__ __launch_bounds__(BLK) void k_pass_v_fin(IterBufs B, BatchGeom g) {
+  const int ii = blockIdx.x;
+  const Inst I = g.inst[ii];
+  if (B.st[ii].phase != RUNNING) return;
+  const dd rv = combine_dd(B.partials + I.blk0, I.nblk);
   if (threadIdx.x != 0) return;
-  SolveState &S = *B.st;
+  SolveState &S = B.st[ii];
   S.alpha = S.rho / rv.hi;
   if (!finite(S.alpha)) { S.status = 5; S.phase = DONE; }
 }
-hipError_t launch_pass_v(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+hipError_t launch_pass_v(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   hipLaunchKernelGGL(k_pass_v, dim3(g.nblk), dim3(BLK), 0, s, B, g);
-  hipLaunchKernelGGL(k_pass_v_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_pass_v_fin, dim3(g.ninst), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }
 
 // s = r - alpha v; partials s.s, max|s|; finalize the half-step test.
-__global__ __launch_bounds__(BLK) void k_pass_s(IterBufs B, Stream1D g) {
-  if (B.st->phase != RUNNING) return;
-  ADR_BLOCK_RANGE(g, beg, end);
-  const double alpha = B.st->alpha;
+__global__ __launch_bounds__(BLK) void k_pass_s(IterBufs B, BatchGeom g) {
+  ADR_BATCH_BLOCK(g);
+  if (B.st[ii].phase != RUNNING) return;
+  const double alpha = B.st[ii].alpha;
+  const double *r = B.r + o, *v = B.v + o;
+  double *sv = B.s + o;
   dd acc[1] = {dd{0.0, 0.0}};
   double mx = 0.0;
   for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    const double sk = fma(-alpha, B.v[k], B.r[k]);
-    B.s[k] = sk;
+    const double sk = fma(-alpha, v[k], r[k]);
+    sv[k] = sk;
     acc[0] = dd_add(acc[0], dd_prod(sk, sk));
     mx = nanmax(mx, fabs(sk));
   }
   block_partials<1, true>(acc, mx, B.partials, g.nblk, blockIdx.x);
 }
-__global__ __launch_bounds__(BLK) void k_pass_s_fin(IterBufs B, Stream1D g) {
-  if (B.st->phase != RUNNING) return;
-  const dd ss = combine_dd(B.partials, g.nblk);
-  const double smax = combine_max(B.partials + (size_t)3 * g.nblk, g.nblk);
+__global__ __launch_bounds__(BLK) void k_pass_s_fin(IterBufs B, BatchGeom g) {
+  const int ii = blockIdx.x;
+  const Inst I = g.inst[ii];
+  if (B.st[ii].phase != RUNNING) return;
+  const dd ss = combine_dd(B.partials + I.blk0, I.nblk);
+  const double smax = combine_max(B.partials + (size_t)3 * g.nblk + I.blk0, I.nblk);
   if (threadIdx.x != 0) return;
-  SolveState &S = *B.st;
+  SolveState &S = B.st[ii];
   const double snorm = sqrt(ss.hi);
   if (!finite(snorm)) { S.status = 5; S.phase = DONE; return; }
   if (snorm < S.thr) {
-    B.hist_l2[S.iter] = snorm;
-    B.hist_max[S.iter] = smax;
+    hist_l2_of(B, ii)[S.iter] = snorm;
+    hist_max_of(B, ii)[S.iter] = smax;
     S.hist_len = S.iter + 1;
     S.half_step = 1;
     S.status = 0;
     S.phase = HALF_STEP;  // x += alpha p^ is left to the x/r kernel
   }
 }
-hipError_t launch_pass_s(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+hipError_t launch_pass_s(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   hipLaunchKernelGGL(k_pass_s, dim3(g.nblk), dim3(BLK), 0, s, B, g);
-  hipLaunchKernelGGL(k_pass_s_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_pass_s_fin, dim3(g.ninst), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }
 
 // t = A z; partials t.s, t.t; finalize omega = (t.s)/(t.t).
-__global__ __launch_bounds__(BLK) void k_pass_t(IterBufs B, Stream1D g) {
-  if (B.st->phase != RUNNING) return;
-  ADR_BLOCK_RANGE(g, beg, end);
+__global__ __launch_bounds__(BLK) void k_pass_t(IterBufs B, BatchGeom g) {
+  ADR_BATCH_BLOCK(g);
+  if (B.st[ii].phase != RUNNING) return;
+  Dia A{B.A.S + o, B.A.W + o, B.A.C + o, B.A.E + o, B.A.N + o};
+  const double *z = B.z + o, *sv = B.s + o;
+  double *t = B.t + o;
   dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
   for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    const int j = (int)fdiv((uint32_t)k, B.fd), i = k - j * B.nx;
-    const double tk = spmv_point(B.A, B.z, k, i, j, B.nx, B.ny);
-    B.t[k] = tk;
-    acc[0] = dd_add(acc[0], dd_prod(tk, B.s[k]));
+    const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
+    const double tk = spmv_point(A, z, k, i, j, I.nx, I.ny);
+    t[k] = tk;
+    acc[0] = dd_add(acc[0], dd_prod(tk, sv[k]));
     acc[1] = dd_add(acc[1], dd_prod(tk, tk));
   }
   block_partials<2, false>(acc, 0.0, B.partials, g.nblk, blockIdx.x);
 }
-__global__ __launch_bounds__(BLK) void k_pass_t_fin(IterBufs B, Stream1D g) {
-  if (B.st->phase != RUNNING) return;
-  const dd ts = combine_dd(B.partials, g.nblk);
-  const dd tt = combine_dd(B.partials + (size_t)g.nblk, g.nblk);
+__global__ __launch_bounds__(BLK) void k_pass_t_fin(IterBufs B, BatchGeom g) {
+  const int ii = blockIdx.x;
+  const Inst I = g.inst[ii];
+  if (B.st[ii].phase != RUNNING) return;
+  const dd ts = combine_dd(B.partials + I.blk0, I.nblk);
+  const dd tt = combine_dd(B.partials + (size_t)g.nblk + I.blk0, I.nblk);
   if (threadIdx.x != 0) return;
-  SolveState &S = *B.st;
+  SolveState &S = B.st[ii];
   S.omega = ts.hi / tt.hi;
   if (!finite(S.omega)) { S.status = 5; S.phase = DONE; }
 }
-hipError_t launch_pass_t(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+hipError_t launch_pass_t(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   hipLaunchKernelGGL(k_pass_t, dim3(g.nblk), dim3(BLK), 0, s, B, g);
-  hipLaunchKernelGGL(k_pass_t_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_pass_t_fin, dim3(g.ninst), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }
 
 // x = fma(omega, z, fma(alpha, p^, x)); r = fma(-omega, t, s); partials
 // r.r, r^.r, max|r|; finalize: history, stopping tests, next beta.
 // After a half-step exit: x = fma(alpha, p^, x) only.
-__global__ __launch_bounds__(BLK) void k_pass_xr(IterBufs B, Stream1D g) {
-  const int phase = B.st->phase;
+__global__ __launch_bounds__(BLK) void k_pass_xr(IterBufs B, BatchGeom g) {
+  ADR_BATCH_BLOCK(g);
+  const int phase = B.st[ii].phase;
   if (phase == DONE) return;
-  ADR_BLOCK_RANGE(g, beg, end);
-  const double alpha = B.st->alpha;
+  const double alpha = B.st[ii].alpha;
+  double *x = B.x + o;
+  const double *ph = B.ph + o;
   if (phase == HALF_STEP) {
-    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) B.x[k] = fma(alpha, B.ph[k], B.x[k]);
+    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) x[k] = fma(alpha, ph[k], x[k]);
     return;
   }
-  const double omega = B.st->omega;
+  const double omega = B.st[ii].omega;
+  const double *z = B.z + o, *t = B.t + o, *sv = B.s + o, *rh = B.rh + o;
+  double *r = B.r + o;
   dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
   double mx = 0.0;
   for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    B.x[k] = fma(omega, B.z[k], fma(alpha, B.ph[k], B.x[k]));
-    const double rk = fma(-omega, B.t[k], B.s[k]);
-    B.r[k] = rk;
+    x[k] = fma(omega, z[k], fma(alpha, ph[k], x[k]));
+    const double rk = fma(-omega, t[k], sv[k]);
+    r[k] = rk;
     acc[0] = dd_add(acc[0], dd_prod(rk, rk));
-    acc[1] = dd_add(acc[1], dd_prod(B.rh[k], rk));
+    acc[1] = dd_add(acc[1], dd_prod(rh[k], rk));
     mx = nanmax(mx, fabs(rk));
   }
   block_partials<2, true>(acc, mx, B.partials, g.nblk, blockIdx.x);
 }
-__global__ __launch_bounds__(BLK) void k_pass_xr_fin(IterBufs B, Stream1D g) {
-  const int phase = B.st->phase;
+__global__ __launch_bounds__(BLK) void k_pass_xr_fin(IterBufs B, BatchGeom g) {
+  const int ii = blockIdx.x;
+  const Inst I = g.inst[ii];
+  const int phase = B.st[ii].phase;
   if (phase == DONE) return;
   if (phase == HALF_STEP) {
-    if (threadIdx.x == 0) B.st->phase = DONE;
+    if (threadIdx.x == 0) B.st[ii].phase = DONE;
     return;
   }
-  const dd rr = combine_dd(B.partials, g.nblk);
-  const dd rhr = combine_dd(B.partials + (size_t)g.nblk, g.nblk);
-  const double rmax = combine_max(B.partials + (size_t)3 * g.nblk, g.nblk);
+  const dd rr = combine_dd(B.partials + I.blk0, I.nblk);
+  const dd rhr = combine_dd(B.partials + (size_t)g.nblk + I.blk0, I.nblk);
+  const double rmax = combine_max(B.partials + (size_t)3 * g.nblk + I.blk0, I.nblk);
   if (threadIdx.x != 0) return;
-  SolveState &S = *B.st;
+  SolveState &S = B.st[ii];
   const int i = S.iter;
   const double rnorm = sqrt(rr.hi);
-  B.hist_l2[i] = rnorm;
-  B.hist_max[i] = rmax;
+  hist_l2_of(B, ii)[i] = rnorm;
+  hist_max_of(B, ii)[i] = rmax;
   S.hist_len = i + 1;
   S.rho_prev = S.rho;
   S.rho = rhr.hi;
@@ -572,26 +631,34 @@ __global__ __launch_bounds__(BLK) void k_pass_xr_fin(IterBufs B, Stream1D g) {
   if (S.rho == 0.0) { S.status = 2; S.phase = DONE; return; }
   S.beta = (S.rho / S.rho_prev) * (S.alpha / S.omega);
 }
-hipError_t launch_pass_xr(const IterBufs &B, const Stream1D &g, hipStream_t s) {
+hipError_t launch_pass_xr(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   hipLaunchKernelGGL(k_pass_xr, dim3(g.nblk), dim3(BLK), 0, s, B, g);
-  hipLaunchKernelGGL(k_pass_xr_fin, dim3(1), dim3(BLK), 0, s, B, g);
+  hipLaunchKernelGGL(k_pass_xr_fin, dim3(g.ninst), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }
 
-// ||b - A x||_2 (double-double), written to *out.
-__global__ __launch_bounds__(BLK) void k_true_res(IterBufs B, Stream1D g) {
-  ADR_BLOCK_RANGE(g, beg, end);
+// ||b - A x||_2^2 (double-double) per instance, into SolveState::true_res2.
+__global__ __launch_bounds__(BLK) void k_true_res(IterBufs B, BatchGeom g) {
+  ADR_BATCH_BLOCK(g);
+  Dia A{B.A.S + o, B.A.W + o, B.A.C + o, B.A.E + o, B.A.N + o};
+  const double *bb = B.b + o, *x = B.x + o;
   dd acc[1] = {dd{0.0, 0.0}};
   for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    const int j = (int)fdiv((uint32_t)k, B.fd), i = k - j * B.nx;
-    const double e = B.b[k] - spmv_point(B.A, B.x, k, i, j, B.nx, B.ny);
+    const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
+    const double e = bb[k] - spmv_point(A, x, k, i, j, I.nx, I.ny);
     acc[0] = dd_add(acc[0], dd_prod(e, e));
   }
   block_partials<1, false>(acc, 0.0, B.partials, g.nblk, blockIdx.x);
 }
-hipError_t launch_true_residual(const IterBufs &B, const Stream1D &g, double *out, hipStream_t s) {
+__global__ __launch_bounds__(BLK) void k_true_res_fin(IterBufs B, BatchGeom g) {
+  const int ii = blockIdx.x;
+  const Inst I = g.inst[ii];
+  const dd e = combine_dd(B.partials + I.blk0, I.nblk);
+  if (threadIdx.x == 0) B.st[ii].true_res2 = e.hi;
+}
+hipError_t launch_true_residual(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   hipLaunchKernelGGL(k_true_res, dim3(g.nblk), dim3(BLK), 0, s, B, g);
-  hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(BLK), 0, s, B.partials, g.nblk, out);
+  hipLaunchKernelGGL(k_true_res_fin, dim3(g.ninst), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }
 

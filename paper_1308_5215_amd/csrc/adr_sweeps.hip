@@ -80,6 +80,17 @@ __device__ __forceinline__ double handoff_take(const uint64_t *p, bool need, uin
   return need ? __longlong_as_double((long long)b) : 0.0;
 }
 
+// Instance owning global strip t (instances sorted by strip0).
+__device__ __forceinline__ int find_strip_inst(const Inst *inst, int ninst, int t) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].strip0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ void strip_finish(const SweepSync &sy, int nstrips) {
   if (threadIdx.x == 0) {
     const unsigned fin = atomicAdd(&sy.ticket[1], 1u);
@@ -100,12 +111,12 @@ __device__ __forceinline__ void strip_finish(const SweepSync &sy, int nstrips) {
 // PREC 0: factors FP64; 1: factors FP32, arithmetic FP64; 2: arithmetic FP32.
 // ---------------------------------------------------------------------------
 struct SweepParams {
-  int nx, ny, nstrips;
-  const double *v;      // q (L) or y (U)
+  BatchGeom g;
+  const double *v;      // q (L) or y (U), batched
   const void *f1, *f2, *f3;   // lw, ls (L) or E, N, invd (U); double or float per PREC
   double *out;
   SweepSync sync;
-  const int32_t *phase;
+  const SolveState *st;  // per-instance state (null: always run)
 };
 
 // ---------------------------------------------------------------------------
@@ -179,12 +190,14 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   __shared__ __align__(16) double s_out[2][L][PITCH];
   __shared__ __align__(8) int s_flag[NC][2];   // [slot]{loaded, ghost}: chunk index + 1
   __shared__ int s_computed, s_stored;
-  __shared__ int s_strip;
+  __shared__ int s_strip, s_inst;
 
-  if (p.phase && *p.phase != RUNNING) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (tid == 0) {
-    s_strip = (int)atomicAdd(&p.sync.ticket[0], 1u);
+    const int t = (int)atomicAdd(&p.sync.ticket[0], 1u);
+    const int ii = find_strip_inst(p.g.inst, p.g.ninst, t);
+    s_inst = ii;
+    s_strip = t - p.g.inst[ii].strip0;
     s_computed = 0;
     s_stored = 0;
   }
@@ -199,18 +212,26 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   }
   __syncthreads();
   const int strip = s_strip;
-  const int nx = p.nx, ny = p.ny;
+  const Inst I = p.g.inst[s_inst];
+  if (p.st && p.st[s_inst].phase != RUNNING) {   // this instance has stopped
+    strip_finish(p.sync, p.g.nstrips);
+    return;
+  }
+  const int nx = I.nx, ny = I.ny;
   const int base = strip * R;
   const int rows = min(R, ny - base);
   const bool has_prev = strip > 0, has_next = base + R < ny;
   const int nchunks = (nx + rows + W - 1) / W;
   const int lr = lane / W, lc = lane % W;   // tile (row-in-pass, column) for loads and stores
+  const double *vin = p.v + I.off;
+  double *vout = p.out + I.off;
+  const uint64_t *ho_base = p.sync.handoff + I.ho_off;
   auto grow = [&](int l) { return OP == 0 ? base + l - 1 : ny - base - l; };
   auto gcol = [&](int co) { return OP == 0 ? co : nx - 1 - co; };
 
   if (wave >= 3) {
     // ------------------------------------------------------------ loaders
-    const TF *f1 = (const TF *)p.f1, *f2 = (const TF *)p.f2, *f3 = (const TF *)p.f3;
+    const TF *f1 = (const TF *)p.f1 + I.off, *f2 = (const TF *)p.f2 + I.off, *f3 = (const TF *)p.f3 + I.off;
     for (int c = wave - 3; c < nchunks; c += NLD) {
       CT b[NIN][NP];
 #pragma unroll
@@ -219,7 +240,7 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
         const int co = c * W + lc - l;
         const bool ok = (l <= rows) && (co >= 0) && (co < nx);
         const size_t k = ok ? (size_t)grow(l) * nx + gcol(co) : 0;
-        b[0][q] = ok ? (CT)p.v[k] : (CT)0;
+        b[0][q] = ok ? (CT)vin[k] : (CT)0;
         b[1][q] = ok ? (CT)f1[k] : (CT)0;
         b[2][q] = ok ? (CT)f2[k] : (CT)0;
         if (NIN == 4) b[NIN - 1][q] = ok ? (CT)f3[k] : (CT)0;
@@ -247,7 +268,7 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
       constexpr int CPW = 64 / W;   // chunks per window
       constexpr int NS = 1;         // samples in flight
       constexpr uint64_t GM = (W == 64) ? ~0ull : ((1ull << W) - 1);
-      const uint64_t *ho_in = p.sync.handoff + (size_t)(strip - 1) * nx;
+      const uint64_t *ho_in = ho_base + (size_t)(strip - 1) * nx;
       unsigned idle = 0;
       bool dead = false;
       int next = 0;
@@ -308,13 +329,13 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
         const int l = 1 + q * RPP + lr;
         const int co = c * W + lc - l;
         const bool ok = (l <= rows) && (co >= 0) && (co < nx);
-        if (ok) p.out[(size_t)grow(l) * nx + gcol(co)] = s_out[b][l][lc];
+        if (ok) vout[(size_t)grow(l) * nx + gcol(co)] = s_out[b][l][lc];
       }
       lds_put(&s_stored, c + 1);
     }
   } else {
     // ------------------------------------------------------------- compute
-    uint64_t *ho_out = p.sync.handoff + (size_t)strip * nx;
+    uint64_t *ho_out = const_cast<uint64_t *>(ho_base) + (size_t)strip * nx;
     const int row = lane < L ? lane : L - 1;
     CT west = (CT)0;
     uint64_t fl = lds_peek_pair(&s_flag[0][0]);
@@ -367,7 +388,7 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
     }
   }
   __syncthreads();
-  strip_finish(p.sync, p.nstrips);
+  strip_finish(p.sync, p.g.nstrips);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,12 +400,12 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
 // the strip below: its invd from the hand-off buffer, its N from A.
 // ---------------------------------------------------------------------------
 struct FactorParams {
-  int nx, ny, nstrips;
+  BatchGeom g;
   Dia A;
   Factors64 f;
   Factors32 h;   // optional FP32 copies (null pointers: not written)
   SweepSync sync;
-  unsigned long long *bad;   // min over bad pivot indices (pre-set to ~0)
+  unsigned long long *bad;   // per instance: min over bad pivot indices (pre-set to ~0)
 };
 
 template <int R, int W>
@@ -395,18 +416,22 @@ __global__ __launch_bounds__(64) void k_ilu0(FactorParams p) {
   const int lane = threadIdx.x;
   unsigned tk = 0;
   if (lane == 0) tk = atomicAdd(&p.sync.ticket[0], 1u);
-  const int strip = __builtin_amdgcn_readfirstlane((int)tk);
-  const int nx = p.nx, ny = p.ny;
+  const int t = __builtin_amdgcn_readfirstlane((int)tk);
+  const int ii = find_strip_inst(p.g.inst, p.g.ninst, t);
+  const Inst I = p.g.inst[ii];
+  const int strip = t - I.strip0;
+  const int nx = I.nx, ny = I.ny;
   const int base = strip * R;
   const int rows = min(R, ny - base);
   const bool has_prev = strip > 0, has_next = base + R < ny;
-  const uint64_t *ho_in = p.sync.handoff + (size_t)(has_prev ? strip - 1 : 0) * nx;
-  uint64_t *ho_out = p.sync.handoff + (size_t)strip * nx;
+  const uint64_t *ho_in = p.sync.handoff + I.ho_off + (size_t)(has_prev ? strip - 1 : 0) * nx;
+  uint64_t *ho_out = p.sync.handoff + I.ho_off + (size_t)strip * nx;
   const int nsteps = nx + rows;
   const int nchunks = (nsteps + W - 1) / W;
   const int lrow = lane / W, lcol = lane % W;
   bool dead = false;
-  const double *in[NIN] = {p.A.S, p.A.W, p.A.C, p.A.E, p.A.N};
+  const int64_t o = I.off;
+  const double *in[NIN] = {p.A.S + o, p.A.W + o, p.A.C + o, p.A.E + o, p.A.N + o};
 
   double stg[NIN][NP];
   auto issue = [&](int c) {
@@ -460,7 +485,7 @@ __global__ __launch_bounds__(64) void k_ilu0(FactorParams p) {
       const bool bad = valid && (d == 0.0 || !isfinite(d));
       double invd = (valid && !bad) ? 1.0 / d : 0.0;
       if (lane == 0) invd = C;
-      if (bad) atomicMin(p.bad, (unsigned long long)((size_t)(base + lane - 1) * nx + co));
+      if (bad) atomicMin(p.bad + ii, (unsigned long long)((size_t)(base + lane - 1) * nx + co));
       if (lane < L) {
         s_out[0][lane][w] = lw;
         s_out[1][lane][w] = ls;
@@ -478,7 +503,7 @@ __global__ __launch_bounds__(64) void k_ilu0(FactorParams p) {
       const int co = c * W + lcol - l;
       const bool ok = (l >= 1) && (l <= rows) && (co >= 0) && (co < nx);
       if (ok) {
-        const size_t k = (size_t)(base + l - 1) * nx + co;
+        const size_t k = (size_t)o + (size_t)(base + l - 1) * nx + co;
         p.f.lw[k] = s_out[0][l][lcol];
         p.f.ls[k] = s_out[1][l][lcol];
         p.f.invd[k] = s_out[2][l][lcol];
@@ -493,98 +518,77 @@ __global__ __launch_bounds__(64) void k_ilu0(FactorParams p) {
     }
     __syncthreads();
   }
-  strip_finish(p.sync, p.nstrips);
+  strip_finish(p.sync, p.g.nstrips);
 }
 
 // ---------------------------------------------------------------------------
-// Launchers.
+// Launchers.  One launch covers every strip of every instance of the batch.
 // ---------------------------------------------------------------------------
-static int strips_of(int ny, int rows) { return (ny + rows - 1) / rows; }
-
-hipError_t launch_ilu0(const Dia &A, int nx, int ny, int rows, Factors64 f64, Factors32 f32,
+hipError_t launch_ilu0(const Dia &A, const BatchGeom &g, Factors64 f64, Factors32 f32,
                        const SweepSync &sync, int64_t *bad, hipStream_t s) {
   FactorParams p;
-  p.nx = nx;
-  p.ny = ny;
+  p.g = g;
   p.A = A;
   p.f = f64;
   p.h = f32;
   p.sync = sync;
   p.bad = (unsigned long long *)bad;
-  switch (rows) {
-    case 15:
-      p.nstrips = strips_of(ny, 15);
-      hipLaunchKernelGGL((k_ilu0<15, 32>), dim3(p.nstrips), dim3(64), 0, s, p);
-      break;
-    case 31:
-      p.nstrips = strips_of(ny, 31);
-      hipLaunchKernelGGL((k_ilu0<31, 32>), dim3(p.nstrips), dim3(64), 0, s, p);
-      break;
-    case 63:
-      p.nstrips = strips_of(ny, 63);
-      hipLaunchKernelGGL((k_ilu0<63, 16>), dim3(p.nstrips), dim3(64), 0, s, p);
-      break;
-    default:
-      return hipErrorInvalidValue;
+  switch (g.rows) {
+    case 15: hipLaunchKernelGGL((k_ilu0<15, 32>), dim3(g.nstrips), dim3(64), 0, s, p); break;
+    case 31: hipLaunchKernelGGL((k_ilu0<31, 32>), dim3(g.nstrips), dim3(64), 0, s, p); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <int OP, int PREC>
-static hipError_t launch_sweep_t(int nx, int ny, int rows, SweepParams p, hipStream_t s) {
-  p.nx = nx;
-  p.ny = ny;
-  switch (rows) {
-    case 15:
-      p.nstrips = strips_of(ny, 15);
-      hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC>), dim3(p.nstrips), dim3(512), 0, s, p);
-      break;
-    case 31:
-      p.nstrips = strips_of(ny, 31);
-      hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC>), dim3(p.nstrips), dim3(512), 0, s, p);
-      break;
-    default:
-      return hipErrorInvalidValue;
+static hipError_t launch_sweep_t(const SweepParams &p, hipStream_t s) {
+  switch (p.g.rows) {
+    case 15: hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
+    case 31: hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_lsweep(int nx, int ny, int rows, int precision, const Factors64 &f64,
-                         const Factors32 &f32, const double *q, double *y, const SweepSync &sync,
-                         const int32_t *phase, hipStream_t s) {
+hipError_t launch_lsweep(const BatchGeom &g, int precision, const Factors64 &f64, const Factors32 &f32,
+                         const double *q, double *y, const SweepSync &sync, const SolveState *st,
+                         hipStream_t s) {
   SweepParams p{};
+  p.g = g;
   p.v = q;
   p.out = y;
   p.sync = sync;
-  p.phase = phase;
+  p.st = st;
   if (precision == 0) {
     p.f1 = f64.lw;
     p.f2 = f64.ls;
-    return launch_sweep_t<0, 0>(nx, ny, rows, p, s);
+    return launch_sweep_t<0, 0>(p, s);
   }
   p.f1 = f32.lw;
   p.f2 = f32.ls;
-  return precision == 1 ? launch_sweep_t<0, 1>(nx, ny, rows, p, s) : launch_sweep_t<0, 2>(nx, ny, rows, p, s);
+  return precision == 1 ? launch_sweep_t<0, 1>(p, s) : launch_sweep_t<0, 2>(p, s);
 }
 
-hipError_t launch_usweep(int nx, int ny, int rows, int precision, const Dia &A,
-                         const Factors64 &f64, const Factors32 &f32, const double *y, double *z,
-                         const SweepSync &sync, const int32_t *phase, hipStream_t s) {
+hipError_t launch_usweep(const BatchGeom &g, int precision, const Dia &A, const Factors64 &f64,
+                         const Factors32 &f32, const double *y, double *z, const SweepSync &sync,
+                         const SolveState *st, hipStream_t s) {
   SweepParams p{};
+  p.g = g;
   p.v = y;
   p.out = z;
   p.sync = sync;
-  p.phase = phase;
+  p.st = st;
   if (precision == 0) {
     p.f1 = A.E;
     p.f2 = A.N;
     p.f3 = f64.invd;
-    return launch_sweep_t<1, 0>(nx, ny, rows, p, s);
+    return launch_sweep_t<1, 0>(p, s);
   }
   p.f1 = f32.E;
   p.f2 = f32.N;
   p.f3 = f32.invd;
-  return precision == 1 ? launch_sweep_t<1, 1>(nx, ny, rows, p, s) : launch_sweep_t<1, 2>(nx, ny, rows, p, s);
+  return precision == 1 ? launch_sweep_t<1, 1>(p, s) : launch_sweep_t<1, 2>(p, s);
 }
 
 }  // namespace adr

@@ -303,3 +303,54 @@ def test_mixed_precision_solve(adr, precision, scheme):
     # the discretisation error is within 1% of the FP64 oracle's
     e_mixed, e64 = orc.max_error(P, x), orc.max_error(P, ref64.x)
     assert abs(e_mixed - e64) <= 0.01 * e64
+
+
+# --------------------------------------------------------------------------
+# Batches: many instances advanced by the same launches
+# --------------------------------------------------------------------------
+
+BATCH = [  # eps, X, Y, nx, ny, scheme, bc
+    (0.1, 1.0, 1.0, 64, 64, 0, 0), (2.0, 1.0, 1.0, 37, 53, 1, 1), (0.01, 1.0, 1.0, 130, 67, 1, 0),
+    (0.5, 1.0, 1.0, 1, 40, 1, 0), (0.5, 1.0, 1.0, 45, 1, 0, 0), (0.01, 1.0, 1.0, 96, 96, 0, 1),
+    (0.003, 0.7, 1.6, 160, 128, 0, 0), (0.2, 1.9, 0.6, 33, 200, 1, 1)]
+
+
+@pytest.mark.parametrize("with_field", [False, True])
+def test_batch_matches_oracle_instance_by_instance(adr, with_field):
+    say("batch", with_field)
+    cols = list(zip(*BATCH))
+    fields, flat = [], None
+    if with_field:
+        for k, (eps, X, Y, nx, ny, sc, bc) in enumerate(BATCH):
+            fields.append(fields_grf(nx, ny, X, Y, k))
+        flat = np.concatenate(fields)
+    b = adr.assemble_batch(*cols, field=None if flat is None else cuda(flat), amp=0.1)
+    b.ilu0()
+    res = b.solve(1e-10, 1500)
+    xs = [host(v) for v in b.split(res.x)]
+    for k, (eps, X, Y, nx, ny, sc, bc) in enumerate(BATCH):
+        P = oracle_problem(eps, X, Y, nx, ny, sc, bc, field=fields[k] if with_field else None,
+                           amp=0.1 if with_field else 0.0)
+        ref = orc.bicgstab(P, orc.ilu0(P), tol=1e-10, maxit=1500)
+        assert res.status[k] == ref.status, (k, res.status[k], ref.status)
+        assert res.iters[k] == ref.iters, (k, res.iters[k], ref.iters)
+        np.testing.assert_array_equal(res.hist_l2[k], ref.hist_l2)
+        assert equal(xs[k], ref.x), k
+
+
+def fields_grf(nx, ny, X, Y, k):
+    return fields.gaussian_random_field(nx, ny, X / (nx + 1), Y / (ny + 1), length=0.1, seed=1308, instance=k).ravel()
+
+
+def test_batch_autotune_keeps_results(adr):
+    say("autotune")
+    cols = list(zip(*BATCH[:4]))
+    b = adr.assemble_batch(*cols)
+    b.ilu0()
+    r0 = b.solve(1e-10, 500)
+    x0 = host(r0.x).copy()
+    rows, ms = b.autotune()
+    assert rows in (15, 31) and ms > 0
+    r1 = b.solve(1e-10, 500)
+    assert np.array_equal(host(r1.x), x0)
+    assert list(r1.iters) == list(r0.iters)
