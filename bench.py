@@ -56,6 +56,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--workload", choices=("single", "batch"), default="single")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-precision", default="fp32_factors")
+    ap.add_argument("--batch-maxit", type=int, default=2000)
+    ap.add_argument("--sequential-sample", type=int, default=0,
+                    help="solve only this many instances one at a time for the comparison (0 = all)")
     return ap.parse_args()
 
 
@@ -88,12 +94,105 @@ def traffic_for(kernel, workload):
         return None
 
 
+def run_batch(args):
+    """Batched workload: many uneven instances (grid n x n, n in 128..1024 step
+    32, eps log-uniform in [1e-3, 1], X, Y in [0.5, 2], scheme and boundary
+    type with p = 1/2, forcing = manufactured + Gaussian random field of length
+    0.1 and amplitude 0.1 max|f|), FP32 preconditioner with FP64 Krylov, one
+    launch per step for the whole batch.  Compared with the same instances
+    solved one at a time by the single-instance path."""
+    import numpy as np
+    import torch
+    import paper_1308_5215_amd as adr
+    from synthetic import fields
+
+    torch.cuda.set_device(0)
+    inst = fields.batch_instances(args.batch_count, seed=1308)
+    t0 = time.perf_counter()
+    flds = [fields.gaussian_random_field(d["n"], d["n"], d["X"] / (d["n"] + 1), d["Y"] / (d["n"] + 1),
+                                         length=0.1, seed=1308, instance=k).ravel() for k, d in enumerate(inst)]
+    log("fields: %.1f s" % (time.perf_counter() - t0))
+    flat = torch.from_numpy(np.concatenate(flds)).cuda()
+    cols = dict(eps=[d["eps"] for d in inst], X=[d["X"] for d in inst], Y=[d["Y"] for d in inst],
+                nx=[d["n"] for d in inst], ny=[d["n"] for d in inst], scheme=[d["scheme"] for d in inst],
+                bc=[d["bc"] for d in inst])
+    N = [d["n"] * d["n"] for d in inst]
+
+    def batch_once():
+        b = adr.assemble_batch(cols["eps"], cols["X"], cols["Y"], cols["nx"], cols["ny"], cols["scheme"],
+                               cols["bc"], field=flat, amp=0.1)
+        b.ilu0(args.batch_precision)
+        rows, ms = b.autotune()
+        res = b.solve(tol=args.tol, maxit=args.batch_maxit)
+        return b, rows, ms, res
+
+    log("batch warmup")
+    for _ in range(args.warmup):
+        batch_once()
+    torch.cuda.synchronize()
+    log("batch timed: %d step(s)" % args.steps)
+    times, t0 = [], time.perf_counter()
+    for _ in range(args.steps):
+        b, rows, ms_apply, res = batch_once()
+        times.append(res.solve_ms)
+        log("  batch solve %.1f ms, rows %d (autotuned, %.2f ms per M^-1)" % (res.solve_ms, rows, ms_apply))
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    st = np.asarray(res.status)
+    its = np.asarray(res.iters)
+    counts = {int(k): int((st == k).sum()) for k in np.unique(st)}
+    work = float(sum(N[k] * its[k] for k in range(len(inst))))
+    batch_s = float(np.mean(times)) / 1e3
+    xb = [v.clone() for v in b.split(res.x)]
+    del b
+
+    # the same instances one at a time
+    sample = range(len(inst)) if args.sequential_sample <= 0 else \
+        np.linspace(0, len(inst) - 1, args.sequential_sample).round().astype(int)
+    seq_ms, seq_work, maxdiff = 0.0, 0.0, 0.0
+    log("sequential: %d instance(s)" % len(sample))
+    for k in sample:
+        d = inst[k]
+        prob = adr.assemble(d["eps"], d["X"], d["Y"], d["n"], d["n"], d["scheme"], d["bc"],
+                            field=flat[sum(N[:k]):sum(N[:k + 1])], amp=0.1)
+        prob.ilu0(args.batch_precision)
+        r1 = prob.solve(tol=args.tol, maxit=args.batch_maxit)
+        seq_ms += r1.solve_ms
+        seq_work += N[k] * r1.iters
+        if r1.status == 0 and st[k] == 0:
+            maxdiff = max(maxdiff, float((r1.x - xb[k]).abs().max() / xb[k].abs().max().clamp_min(1e-300)))
+        del prob, r1
+    scale = len(inst) / len(sample)
+    seq_s = seq_ms * scale / 1e3
+    out = {
+        "metric": "time to rel-resid 1e-10, batched instances (FP32 preconditioner, FP64 Krylov)",
+        "value": round(batch_s, 4), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%d instances, n in 128..1024 step 32, eps log-uniform [1e-3,1], X,Y in [0.5,2], "
+                               "random scheme/bc, manufactured f + GRF (length 0.1, amp 0.1 max|f|)" % len(inst),
+                   "precision": args.batch_precision, "tol": args.tol, "maxit": args.batch_maxit,
+                   "total_unknowns": int(sum(N)), "seed": 1308},
+        "statuses": counts,
+        "unknown_passes_per_s": round(work / batch_s, 1),
+        "hbm_gbs_algorithmic": round(BYTES["iteration"] * work / batch_s / 1e9, 1),
+        "sequential": {"solve_s": round(seq_s, 3), "instances_timed": len(sample),
+                       "extrapolated": len(sample) != len(inst),
+                       "speedup_batched": round(seq_s / batch_s, 2) if batch_s > 0 else None,
+                       "max_rel_diff_vs_batched": maxdiff},
+        "sweep_rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return run_batch(args)
     import numpy as np
     import torch
     import paper_1308_5215_amd as adr
