@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import (OK, MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE, UPWIND, CENTERED,
                    DIRICHLET, NEUMANN_XY, FP64, FP32_FACTORS, FP32_SWEEPS, AdrError)
 
-__all__ = ["assemble", "assemble_batch", "Problem", "Batch", "SolveResult", "BatchResult", "dot", "AdrError", "OK", "MAXIT", "BREAKDOWN_RHO",
+__all__ = ["assemble", "assemble_batch", "WarmStartNet", "cnn_param_count", "Problem", "Batch", "SolveResult", "BatchResult", "dot", "AdrError", "OK", "MAXIT", "BREAKDOWN_RHO",
            "OMEGA_ZERO", "ZERO_PIVOT", "NONFINITE", "UPWIND", "CENTERED", "DIRICHLET", "NEUMANN_XY",
            "FP64", "FP32_FACTORS", "FP32_SWEEPS"]
 
@@ -266,6 +266,29 @@ class Batch:
             np.array([i.bnorm for i in info]), np.array([i.true_relres for i in info]),
             info[0].solve_ms if self.count else 0.0, st)
 
+    # -- learned initial guess (include/adr_cnn.h) --
+    def features(self, first=0, count=None, out=None):
+        """Input fields of instances [first, first + count) as a bfloat16
+        tensor [count, ny+2, nx+2, 32] (adr_cnn_features)."""
+        torch = _torch()
+        count = self.count - first if count is None else int(count)
+        p = self.params[first]
+        shape = (count, p["ny"] + 2, p["nx"] + 2, 32)
+        t = out if out is not None else torch.empty(shape, dtype=torch.bfloat16, device="cuda")
+        if t.dtype != torch.bfloat16 or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError("out must be a contiguous bfloat16 tensor of shape %s" % (shape,))
+        _lib.check(_lib.load().adr_cnn_features(self._h, int(first), count, ctypes.c_void_p(t.data_ptr())))
+        return t
+
+    def warm_start(self, net, out=None):
+        """The network's initial guess for every instance with the zero-guess
+        fallback (adr_batch_warm_start).  Returns (x0 tensor, used flags)."""
+        torch = _torch()
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        used = (ctypes.c_int32 * self.count)()
+        _lib.check(_lib.load().adr_batch_warm_start(self._h, net._h, _dev_f64(x, self.n, "out"), used))
+        return x, np.array(used[:], dtype=bool)
+
 
 def assemble_batch(eps, X, Y, nx, ny, scheme, bc, field=None, amp=0.0, stream=None):
     """Batched Section 4 assembly (adr_batch_assemble).  Every argument but
@@ -284,6 +307,9 @@ def assemble_batch(eps, X, Y, nx, ny, scheme, bc, field=None, amp=0.0, stream=No
     params = [dict(eps=float(eps[k]), X=float(X[k]), Y=float(Y[k]), nx=int(nx[k]), ny=int(ny[k]), scheme=sch[k],
                    bc=bcs[k]) for k in range(count)]
     return Batch(h, params, stream)
+
+
+from .cnn import WarmStartNet, param_count as cnn_param_count  # noqa: E402
 
 
 def dot(x, y, stream=None):

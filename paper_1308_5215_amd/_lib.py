@@ -20,6 +20,10 @@ EXPORTS = [
     "adr_get_factors", "adr_spmv", "adr_precond", "adr_lsolve", "adr_usolve", "adr_dot", "adr_device_bytes",
     "adr_set_sweep_rows", "adr_status_str", "adr_last_error", "adr_batch_assemble", "adr_batch_layout",
     "adr_batch_ilu0", "adr_batch_solve", "adr_autotune",
+    # include/adr_cnn.h
+    "adr_cnn_param_count", "adr_cnn_create", "adr_cnn_destroy", "adr_cnn_set_params", "adr_cnn_get_params",
+    "adr_cnn_forward", "adr_cnn_gradient", "adr_cnn_adam", "adr_cnn_train_step", "adr_cnn_features",
+    "adr_batch_warm_start",
 ]
 
 
@@ -83,6 +87,30 @@ def load():
     L.adr_batch_solve.argtypes = [P, f64, i32, P, P, D, D, ctypes.POINTER(SolveInfo)]
     L.adr_autotune.restype = ctypes.c_int
     L.adr_autotune.argtypes = [P, I32P, D]
+    F32P = ctypes.POINTER(ctypes.c_float)
+    f32 = ctypes.c_float
+    L.adr_cnn_param_count.restype = i64
+    L.adr_cnn_param_count.argtypes = []
+    L.adr_cnn_create.restype = ctypes.c_int
+    L.adr_cnn_create.argtypes = [i32, i32, i32, P, ctypes.POINTER(P)]
+    L.adr_cnn_destroy.restype = None
+    L.adr_cnn_destroy.argtypes = [P]
+    L.adr_cnn_set_params.restype = ctypes.c_int
+    L.adr_cnn_set_params.argtypes = [P, F32P]
+    L.adr_cnn_get_params.restype = ctypes.c_int
+    L.adr_cnn_get_params.argtypes = [P, F32P]
+    L.adr_cnn_forward.restype = ctypes.c_int
+    L.adr_cnn_forward.argtypes = [P, P, i32, P]
+    L.adr_cnn_gradient.restype = ctypes.c_int
+    L.adr_cnn_gradient.argtypes = [P, P, P, i32, P, F32P, D]
+    L.adr_cnn_adam.restype = ctypes.c_int
+    L.adr_cnn_adam.argtypes = [P, f32, f32, f32, f32]
+    L.adr_cnn_train_step.restype = ctypes.c_int
+    L.adr_cnn_train_step.argtypes = [P, P, P, i32, f32, D]
+    L.adr_cnn_features.restype = ctypes.c_int
+    L.adr_cnn_features.argtypes = [P, i32, i32, P]
+    L.adr_batch_warm_start.restype = ctypes.c_int
+    L.adr_batch_warm_start.argtypes = [P, P, P, I32P]
     L.adr_status_str.restype = ctypes.c_char_p
     L.adr_status_str.argtypes = [i32]
     L.adr_last_error.restype = ctypes.c_char_p

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadr.so")
-SOURCES = ["adr_capi.hip", "adr_kernels.hip", "adr_sweeps.hip"]
+SOURCES = ["adr_capi.hip", "adr_kernels.hip", "adr_sweeps.hip", "adr_cnn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/adr.h"
+#include "../../include/adr_cnn.h"
 #include "adr_internal.h"
 
 #pragma clang fp contract(off)
@@ -91,6 +92,19 @@ int default_rows(int max_ny) { return max_ny >= 2048 ? 31 : 15; }
 
 }  // namespace
 
+namespace adr {
+int set_error(int st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+void clear_error() { g_last_error.clear(); }
+}  // namespace adr
+
 struct adr_problem {
   int dev = 0;
   hipStream_t stream = nullptr;
@@ -105,6 +119,7 @@ struct adr_problem {
   size_t bytes = 0;
   // matrix (batched)
   double *S = nullptr, *W = nullptr, *C = nullptr, *E = nullptr, *N = nullptr, *rhs = nullptr;
+  double *F = nullptr;         // forcing f per unknown (input of the warm-start network)
   // factors
   double *lw = nullptr, *ls = nullptr, *invd = nullptr;
   float *lw32 = nullptr, *ls32 = nullptr, *invd32 = nullptr, *E32 = nullptr, *N32 = nullptr;
@@ -119,6 +134,7 @@ struct adr_problem {
   int hist_cap = 0;   // maxit + 1 the history buffer was sized for
   double *scal = nullptr;
   int64_t *bad = nullptr;
+  FeatInst *d_feat = nullptr;  // per-instance table of the warm-start input fields
   // wavefront synchronisation
   unsigned *ticket = nullptr;
   uint64_t *handoff = nullptr;
@@ -335,6 +351,7 @@ adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double a
   a.amp = amp;
   a.S = P->S + I.off; a.W = P->W + I.off; a.C = P->C + I.off; a.E = P->E + I.off; a.N = P->N + I.off;
   a.rhs = P->rhs + I.off;
+  a.F = P->F + I.off;
   a.partials = P->partials;
   a.fmax = P->scal;
   if (e == hipSuccess) e = launch_assemble(a, make_geom(I.n), P->stream);
@@ -342,6 +359,26 @@ adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double a
   (void)hipFree(dtab);
   HIP_TRY(e);
   HIP_TRY(es);
+  return ADR_OK;
+}
+
+adr_status ensure_feat_table(adr_problem *P) {
+  if (P->d_feat) return ADR_OK;
+  std::vector<FeatInst> fi((size_t)P->count);
+  for (int k = 0; k < P->count; ++k) {
+    fi[k].eps = P->eps[k];
+    fi[k].X = P->X[k];
+    fi[k].Y = P->Y[k];
+    fi[k].nx = P->nx[k];
+    fi[k].ny = P->ny[k];
+    fi[k].bc = P->bc[k];
+    fi[k].pad = 0;
+    fi[k].off = P->inst[k].off;
+  }
+  size_t b = 0;
+  HIP_TRY(dalloc(&P->d_feat, fi.size(), b));
+  HIP_TRY(hipMemcpy(P->d_feat, fi.data(), fi.size() * sizeof(FeatInst), hipMemcpyHostToDevice));
+  P->bytes += b;
   return ADR_OK;
 }
 
@@ -378,7 +415,7 @@ void adr_destroy(adr_problem *P) {
   if (P->stream) (void)hipStreamSynchronize(P->stream);
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
   if (P->cap) (void)hipStreamDestroy(P->cap);
-  double *dv[] = {P->S, P->W, P->C, P->E, P->N, P->rhs, P->lw, P->ls, P->invd, P->r, P->rh,
+  double *dv[] = {P->S, P->W, P->C, P->E, P->N, P->rhs, P->F, P->lw, P->ls, P->invd, P->r, P->rh,
                   P->p, P->v, P->s, P->t, P->ph, P->z, P->y, P->hist, P->scal};
   for (double *q : dv) dfree(q);
   float *fv[] = {P->lw32, P->ls32, P->invd32, P->E32, P->N32};
@@ -390,6 +427,7 @@ void adr_destroy(adr_problem *P) {
   dfree(P->handoff);
   dfree(P->err);
   dfree(P->d_inst);
+  dfree(P->d_feat);
   if (P->h_st) (void)hipHostFree(P->h_st);
   delete P;
 }
@@ -440,7 +478,7 @@ adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X,
   P->max_ny = *std::max_element(ny, ny + count);
   adr_status st = build_table(P, default_rows(P->max_ny));
   if (st != ADR_OK) return bail(st);
-  double **arrs[] = {&P->S, &P->W, &P->C, &P->E, &P->N, &P->rhs};
+  double **arrs[] = {&P->S, &P->W, &P->C, &P->E, &P->N, &P->rhs, &P->F};
   for (double **q : arrs)
     if (dalloc(q, (size_t)P->ntot, P->bytes) != hipSuccess) return bail(fail(ADR_ERR_NOMEM, "device allocation failed"));
   // partials: 4 slots for every streaming block of the batch, and of one instance's assembly
@@ -793,6 +831,64 @@ adr_status adr_bicgstab_solve(adr_problem *P, double tol, int32_t maxit, const d
     return st;
   }
   return adr_batch_solve(P, tol, maxit, x0, x, hist_l2, hist_max, info);
+}
+
+adr_status adr_cnn_features(const adr_problem *P, int32_t first, int32_t count, uint16_t *out) {
+  g_last_error.clear();
+  if (!P || !out) return fail(ADR_ERR_ARG, "NULL argument");
+  if (first < 0 || count < 1 || (int64_t)first + count > P->count)
+    return fail(ADR_ERR_ARG, "instances [%d, %d) out of range [0, %d)", first, first + count, P->count);
+  for (int k = first; k < first + count; ++k)
+    if (P->nx[k] != P->nx[first] || P->ny[k] != P->ny[first])
+      return fail(ADR_ERR_ARG, "instances %d and %d differ in size", first, k);
+  adr_status st = ensure_feat_table(const_cast<adr_problem *>(P));
+  if (st != ADR_OK) return st;
+  const int H = P->ny[first] + 2, W = P->nx[first] + 2;
+  HIP_TRY(launch_cnn_features(P->d_feat + first, count, H, W, P->F, out, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return ADR_OK;
+}
+
+adr_status adr_batch_warm_start(adr_problem *P, adr_cnn *net, double *x, int32_t *used) {
+  g_last_error.clear();
+  if (!P || !net || !x) return fail(ADR_ERR_ARG, "NULL argument");
+  int H, W, maxB;
+  hipStream_t ns;
+  uint16_t *in;
+  float *u;
+  cnn_shape(net, &H, &W, &maxB, &ns, &in, &u);
+  for (int k = 0; k < P->count; ++k)
+    if (P->nx[k] != W - 2 || P->ny[k] != H - 2)
+      return fail(ADR_ERR_ARG, "instance %d is %d x %d; the network takes %d x %d interior grids", k, P->nx[k],
+                  P->ny[k], W - 2, H - 2);
+  adr_status st = ensure_feat_table(P);
+  if (st != ADR_OK) return st;
+  st = ensure_iter_buffers(P, 0);
+  if (st != ADR_OK) return st;
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  for (int c0 = 0; c0 < P->count; c0 += maxB) {
+    const int nb = std::min(maxB, P->count - c0);
+    HIP_TRY(launch_cnn_features(P->d_feat + c0, nb, H, W, P->F, in, ns));
+    st = adr_cnn_forward(net, in, nb, u);
+    if (st != ADR_OK) return st;
+    HIP_TRY(launch_cnn_extract(P->d_feat + c0, nb, H, W, u, x, ns));
+  }
+  HIP_TRY(hipStreamSynchronize(ns));
+  // fallback test: keep the guess only where ||b - A x0||_2 is finite and below ||b||_2
+  IterBufs B = iter_bufs(P, x, 0.0, 0);
+  HIP_TRY(launch_init(B, P->geom(), P->stream));
+  std::vector<double> h0((size_t)2 * P->count);
+  HIP_TRY(hipMemcpyAsync(P->h_st, P->st, sizeof(SolveState) * (size_t)P->count, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipMemcpyAsync(h0.data(), P->hist, h0.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  for (int k = 0; k < P->count; ++k) {
+    const double bn = P->h_st[k].bnorm, rn = h0[(size_t)2 * k];
+    const bool keep = bn > 0.0 && std::isfinite(rn) && rn < bn;
+    if (!keep) HIP_TRY(launch_fill(x + P->inst[k].off, P->inst[k].n, 0.0, P->stream));
+    if (used) used[k] = keep ? 1 : 0;
+  }
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return ADR_OK;
 }
 
 }  // extern "C"

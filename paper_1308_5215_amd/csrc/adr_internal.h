@@ -12,6 +12,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+struct adr_cnn;
+
 namespace adr {
 
 // Device-resident scalar state of one BiCGSTAB solve.  Written only by the
@@ -94,6 +96,7 @@ struct AssembleArgs {
   const double *field;  // optional
   double amp;
   double *S, *W, *C, *E, *N, *rhs;
+  double *F;           // optional: the forcing f at every unknown
   double2 *partials;   // workspace for the max|f| reduction
   double *fmax;        // device scalar
 };
@@ -140,4 +143,20 @@ hipError_t launch_usweep(const BatchGeom &g, int precision, const Dia &A, const 
                          const Factors32 &f32, const double *y, double *z, const SweepSync &sync,
                          const SolveState *st, hipStream_t s);
 
+// ---- error text shared by every C entry point (adr_capi.hip) ----
+int set_error(int st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+// ---- warm-start network (adr_cnn.hip) ----
+struct FeatInst {
+  double eps, X, Y;
+  int32_t nx, ny, bc, pad;
+  int64_t off;          // offset of the instance in the batched vectors
+};
+hipError_t launch_cnn_features(const FeatInst *fi_dev, int count, int H, int W, const double *F,
+                               uint16_t *out, hipStream_t s);
+hipError_t launch_cnn_extract(const FeatInst *fi_dev, int count, int H, int W, const float *u,
+                              double *x, hipStream_t s);
+// node grid, batch limit, stream and the input/output buffers of a network
+void cnn_shape(const adr_cnn *net, int *H, int *W, int *maxB, hipStream_t *s, uint16_t **in, float **u);
 }  // namespace adr

@@ -281,6 +281,7 @@ __global__ __launch_bounds__(BLK) void k_assemble(AssembleArgs a, Stream1D g, Fa
     a.E[k] = (i == nx - 1) ? 0.0 : e;
     a.N[k] = (j == ny - 1) ? 0.0 : n;
     a.rhs[k] = r;
+    if (a.F) a.F[k] = f;
   }
 }
 

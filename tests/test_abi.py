@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI (no GPU needed): the built library loads and
-exports every function include/adr.h declares; the Python binding refuses to
+exports every function include/*.h declares; the Python binding refuses to
 run without it instead of falling back to anything else."""
 import os
 import re
@@ -8,14 +8,21 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "adr.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("adr.h", "adr_cnn.h")]
 LIB = os.path.join(ROOT, "paper_1308_5215_amd", "libadr.so")
 
 
 def declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(adr_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(adr_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_every_header_is_checked():
+    found = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert found == sorted(os.path.basename(h) for h in HEADERS)
 
 
 def test_header_declares_the_three_calls_of_the_method():
