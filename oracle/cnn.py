@@ -2,7 +2,7 @@
 
 Plain numpy, written from the network's definition rather than from the GPU
 kernels: six 3x3 cross-correlations with zero padding, channels
-5 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, exact GELU x*Phi(x) after the first
+9 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, exact GELU x*Phi(x) after the first
 five, mean squared error over the interior nodes, Adam.  Every sum is in
 FP64.  With ``emulate=True`` the values the network stores in bfloat16
 (input fields, weights, hidden activations, and the gradients entering each
@@ -23,7 +23,8 @@ from scipy.special import erf
 
 from . import core
 
-CIN = (5, 32, 32, 32, 32, 32)
+NFIELD = 9
+CIN = (NFIELD, 32, 32, 32, 32, 32)
 COUT = (32, 32, 32, 32, 32, 1)
 NLAYER = 6
 
@@ -166,13 +167,14 @@ class Adam:
 
 
 def features(eps, X, Y, nx, ny, bc, field=None, amp=0.0):
-    """The five input fields on the (ny+2) x (nx+2) node grid, [ny+2, nx+2, 5]:
-    a/5, b/2, (interior) f/10 or (ring) the boundary datum, log10(eps)/3 and
-    the ring mask (+1 Dirichlet, -1 Neumann, 0 interior).  f is the forcing
-    the solver is assembled with: f_man + amp max|f_man| field."""
+    """The input fields on the (ny+2) x (nx+2) node grid, [ny+2, nx+2, 9]:
+    a/5, b/2, (interior) f/10 or (ring) the boundary datum, log10(eps)/3, the
+    ring mask (+1 Dirichlet, -1 Neumann, 0 interior), x/X, y/Y, X/2 and Y/2.
+    f is the forcing the solver is assembled with:
+    f_man + amp max|f_man| field."""
     H, W = ny + 2, nx + 2
     dx, dy = X / (nx + 1), Y / (ny + 1)
-    out = np.zeros((H, W, 5))
+    out = np.zeros((H, W, NFIELD))
     f = core.forcing(eps, X, Y, nx, ny)
     if field is not None:
         f = f + amp * np.max(np.abs(f)) * np.asarray(field, dtype=np.float64).ravel()
@@ -184,6 +186,10 @@ def features(eps, X, Y, nx, ny, bc, field=None, amp=0.0):
             out[J, I, 0] = (1.0 + x * x) / 5.0
             out[J, I, 1] = X * math.exp(-y) / 2.0
             out[J, I, 3] = math.log10(eps) / 3.0
+            out[J, I, 5] = x / X
+            out[J, I, 6] = y / Y
+            out[J, I, 7] = X / 2.0
+            out[J, I, 8] = Y / 2.0
             if 1 <= I <= nx and 1 <= J <= ny:
                 out[J, I, 2] = f[J - 1, I - 1] / 10.0
                 continue

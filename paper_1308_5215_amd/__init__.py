@@ -88,7 +88,10 @@ class Problem:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _lib.load().adr_destroy(h)
+            try:
+                _lib.load().adr_destroy(h)
+            except (AttributeError, TypeError):   # interpreter shutdown
+                pass
             self._h = None
 
     def close(self):
@@ -218,7 +221,10 @@ class Batch:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _lib.load().adr_destroy(h)
+            try:
+                _lib.load().adr_destroy(h)
+            except (AttributeError, TypeError):   # interpreter shutdown
+                pass
             self._h = None
 
     def close(self):

@@ -45,7 +45,10 @@ class WarmStartNet:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _lib.load().adr_cnn_destroy(h)
+            try:
+                _lib.load().adr_cnn_destroy(h)
+            except (AttributeError, TypeError):   # interpreter shutdown
+                pass
             self._h = None
 
     def close(self):

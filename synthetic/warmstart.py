@@ -5,7 +5,7 @@ import numpy as np
 from .fields import _rng
 
 # layer channels of the warm-start network (input fields -> u)
-CIN = (5, 32, 32, 32, 32, 32)
+CIN = (9, 32, 32, 32, 32, 32)
 COUT = (32, 32, 32, 32, 32, 1)
 
 

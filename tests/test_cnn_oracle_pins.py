@@ -12,7 +12,7 @@ from synthetic import warmstart as ws
 
 
 def test_param_count_and_layout():
-    assert cnn.param_count() == 38753
+    assert cnn.param_count() == 39905
     p = np.arange(cnn.param_count(), dtype=np.float64)
     layers = cnn.unpack(p)
     assert [w.shape for w, _ in layers] == [(3, 3, ci, co) for ci, co in zip(cnn.CIN, cnn.COUT)]
@@ -93,7 +93,7 @@ def test_backward_matches_finite_differences():
     r = np.random.default_rng(5)
     p = ws.initial_params(7).astype(np.float64)
     p += 0.05 * r.standard_normal(p.size)       # non-zero biases too
-    x = r.standard_normal((2, 6, 5, 5))
+    x = r.standard_normal((2, 6, 5, cnn.NFIELD))
     t = r.standard_normal((2, 4, 3))
     L0, g, _ = cnn.loss_and_grad(p, x, t, emulate=False)
     assert L0 > 0
@@ -118,7 +118,7 @@ def test_backward_matches_finite_differences():
 def test_emulated_rounding_stays_close_to_fp64():
     r = np.random.default_rng(6)
     p = ws.initial_params(1)
-    x = cnn.bf16(r.standard_normal((1, 8, 8, 5)))
+    x = cnn.bf16(r.standard_normal((1, 8, 8, cnn.NFIELD)))
     t = r.standard_normal((1, 6, 6))
     L64, g64, u64 = cnn.loss_and_grad(p, x, t, emulate=False)
     Lq, gq, uq = cnn.loss_and_grad(p, x, t, emulate=True)
@@ -149,7 +149,7 @@ def test_adam_matches_torch():
 def test_features_pinned_to_exact_solution_and_forcing(bc):
     eps, X, Y, nx, ny = 0.05, 1.3, 0.7, 9, 6
     f = cnn.features(eps, X, Y, nx, ny, bc)
-    assert f.shape == (ny + 2, nx + 2, 5)
+    assert f.shape == (ny + 2, nx + 2, cnn.NFIELD)
     dx, dy = X / (nx + 1), Y / (ny + 1)
     fman = core.forcing(eps, X, Y, nx, ny).reshape(ny, nx)
     assert np.allclose(f[1:-1, 1:-1, 2], fman / 10.0, rtol=1e-15, atol=0)
@@ -159,6 +159,8 @@ def test_features_pinned_to_exact_solution_and_forcing(bc):
             x, y = I * dx, J * dy
             assert math.isclose(f[J, I, 0], (1 + x * x) / 5, rel_tol=1e-15)
             assert math.isclose(f[J, I, 1], X * math.exp(-y) / 2, rel_tol=1e-15)
+            assert math.isclose(f[J, I, 5], x / X, rel_tol=1e-15) and math.isclose(f[J, I, 6], y / Y, rel_tol=1e-15)
+            assert f[J, I, 7] == X / 2 and f[J, I, 8] == Y / 2
             ring = not (1 <= I <= nx and 1 <= J <= ny)
             if not ring:
                 assert f[J, I, 4] == 0.0

@@ -22,12 +22,13 @@ def _torch():
 
 
 def _inputs(B, H, W, seed):
-    """bfloat16-exact input fields [B, H, W, 5] (float64) and the 32-channel
-    bfloat16 device tensor holding them."""
+    """bfloat16-exact input fields [B, H, W, NFIELD] (float64) and the
+    32-channel bfloat16 device tensor holding them."""
     torch = _torch()
-    x = ocnn.bf16(ws.random_fields(B, H, W, 5, seed=seed))
+    nf = ocnn.NFIELD
+    x = ocnn.bf16(ws.random_fields(B, H, W, nf, seed=seed))
     pad = np.zeros((B, H, W, 32), dtype=np.float32)
-    pad[..., :5] = x
+    pad[..., :nf] = x
     return x, torch.from_numpy(pad).cuda().to(torch.bfloat16).contiguous()
 
 
@@ -171,13 +172,14 @@ def test_features_match_reference(bc):
                                [n] * count, [n] * count, ["upwind"] * count, bcs, field=fd, amp=0.1)
     got = batch.features().float().cpu().numpy().astype(np.float64)
     assert got.shape == (count, n + 2, n + 2, 32)
-    assert np.all(got[..., 5:] == 0)
+    nf = ocnn.NFIELD
+    assert np.all(got[..., nf:] == 0)
     b = core.DIRICHLET if bc == "dirichlet" else core.NEUMANN
     for k, d in enumerate(inst):
         ref = ocnn.bf16(ocnn.features(d["eps"], d["X"], d["Y"], n, n, b, field=fields[k], amp=0.1))
         # device and host exponentials may differ in the last bit: one bfloat16 step at most
-        assert np.all(np.abs(got[k, ..., :5] - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-30)
-        assert np.mean(got[k, ..., :5] == ref) > 0.99
+        assert np.all(np.abs(got[k, ..., :nf] - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-30)
+        assert np.mean(got[k, ..., :nf] == ref) > 0.99
 
 
 def test_warm_start_falls_back_to_zero_for_a_useless_guess():
