@@ -233,17 +233,23 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
     // ------------------------------------------------------------ loaders
     const TF *f1 = (const TF *)p.f1 + I.off, *f2 = (const TF *)p.f2 + I.off, *f3 = (const TF *)p.f3 + I.off;
     for (int c = wave - 3; c < nchunks; c += NLD) {
-      CT b[NIN][NP];
+      // every load of the tile is issued before any is used (points outside
+      // the strip load element 0 and are zeroed afterwards), so the loads
+      // overlap one another and the wait for the ring slot
+      double bv[NP];
+      TF bf[NIN - 1][NP];
+      bool okq[NP];
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const int l = 1 + q * RPP + lr;
         const int co = c * W + lc - l;
         const bool ok = (l <= rows) && (co >= 0) && (co < nx);
         const size_t k = ok ? (size_t)grow(l) * nx + gcol(co) : 0;
-        b[0][q] = ok ? (CT)vin[k] : (CT)0;
-        b[1][q] = ok ? (CT)f1[k] : (CT)0;
-        b[2][q] = ok ? (CT)f2[k] : (CT)0;
-        if (NIN == 4) b[NIN - 1][q] = ok ? (CT)f3[k] : (CT)0;
+        okq[q] = ok;
+        bv[q] = vin[k];
+        bf[0][q] = f1[k];
+        bf[1][q] = f2[k];
+        if (NIN == 4) bf[NIN - 2][q] = f3[k];
       }
       lds_wait_ge(&s_computed, c - NC + 1);   // ring slot free
       const int sl = c % NC;
@@ -251,8 +257,9 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
       for (int q = 0; q < NP; ++q) {
         const int l = 1 + q * RPP + lr;
         if (l < L) {
+          s_in[sl][0][l][lc] = okq[q] ? (CT)bv[q] : (CT)0;
 #pragma unroll
-          for (int m = 0; m < NIN; ++m) s_in[sl][m][l][lc] = b[m][q];
+          for (int m = 1; m < NIN; ++m) s_in[sl][m][l][lc] = okq[q] ? (CT)bf[m - 1][q] : (CT)0;
         }
       }
       lds_put(&s_flag[sl][0], c + 1);
