@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", choices=("single", "batch", "warmstart"), default="single")
+    ap.add_argument("--workload", choices=("single", "batch", "warmstart", "kernels"), default="single")
     ap.add_argument("--heldout", type=int, default=1000, help="warmstart: held-out instances")
     ap.add_argument("--single-sample", type=int, default=128,
                     help="warmstart: instances also timed one at a time")
@@ -227,6 +227,46 @@ def run_warmstart(args):
     print(json.dumps(out), flush=True)
 
 
+def run_kernels(args):
+    """Each hot-path kernel alone, `--kernel-reps` launches each, on the
+    n x n grid (centered scheme, FP64 factors), then a plain element-wise
+    copy kernel of 1 GiB each way as the reference for hardware counters.  For counter runs:
+        rocprofv3 --pmc FETCH_SIZE -- python bench.py --workload kernels
+    """
+    import torch
+    import paper_1308_5215_amd as adr
+
+    torch.cuda.set_device(0)
+    n = args.n
+    N = n * n
+    prob = adr.assemble(args.eps, 1.0, 1.0, n, n, "centered", "dirichlet")
+    if args.rows:
+        prob.set_sweep_rows(args.rows)
+    prob.ilu0(args.precision)
+    q = torch.randn(N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(q)
+    z = torch.empty_like(q)
+    out = {}
+    for name, fn in (("lsweep", lambda: prob.lsolve(q, out=y)), ("usweep", lambda: prob.usolve(y, out=z)),
+                     ("spmv", lambda: prob.spmv(q, out=z))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.kernel_reps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = round((time.perf_counter() - t0) * 1e6 / args.kernel_reps, 1)
+        log("  %s: %.1f us per launch (host clock)" % (name, out[name]))
+    # a plain element-wise copy kernel (b = a * 1) moving 1 GiB each way
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(args.kernel_reps):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "kernels", "n": n, "reps": args.kernel_reps, "us_per_launch": out,
+                      "copy_bytes_each_way": a.numel() * 8, "sweep_rows": args.rows or "auto",
+                      "precision": args.precision}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -237,6 +277,8 @@ def main():
         return run_batch(args)
     if args.workload == "warmstart":
         return run_warmstart(args)
+    if args.workload == "kernels":
+        return run_kernels(args)
     import numpy as np
     import torch
     import paper_1308_5215_amd as adr
