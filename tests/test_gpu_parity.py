@@ -257,6 +257,58 @@ def test_full_size_prefix_parity(adr, scheme):
     assert equal(x, ref.x)
 
 
+@pytest.mark.slow
+def test_large_grid_prefix_parity(adr):
+    """8192 x 8192, X = 2, Y = 1, eps = 1e-3, centered, FP32-stored factors
+    with FP64 BiCGSTAB (the convection-dominated large grid, in the launch
+    configuration the benchmark uses): the first 2 passes equal the oracle's
+    passes with the same float factors bit for bit."""
+    n = 8192
+    say("large grid prefix")
+    prob = adr.assemble(1e-3, 2.0, 1.0, n, n, 1, 0)
+    prob.ilu0("fp32_factors")
+    res = prob.solve(1e-10, 2)
+    x = host(res.x)
+    del prob
+    P = oracle_problem(1e-3, 2.0, 1.0, n, n, 1, 0)
+    ref = orc.bicgstab(P, orc.round_factors_f32(orc.ilu0(P)), tol=1e-10, maxit=2)
+    assert res.status == ref.status == orc.MAXIT
+    assert np.array_equal(res.hist_l2, ref.hist_l2)
+    assert np.array_equal(res.hist_max, ref.hist_max)
+    assert equal(x, ref.x)
+
+
+@pytest.mark.slow
+def test_batch_workload_sampled_instances_match_oracle(adr):
+    """The 256-instance batched workload in the benchmark's configuration
+    (FP32 factors, autotuned strips, one batch): three of its instances,
+    solved again by the oracle with the same float factors, agree in status,
+    pass count, history and solution bit for bit."""
+    say("batch workload sample")
+    inst = fields.batch_instances(256, seed=1308)
+    flds = [fields.gaussian_random_field(d["n"], d["n"], d["X"] / (d["n"] + 1), d["Y"] / (d["n"] + 1),
+                                        length=0.1, seed=1308, instance=k).ravel() for k, d in enumerate(inst)]
+    cols = ([d["eps"] for d in inst], [d["X"] for d in inst], [d["Y"] for d in inst], [d["n"] for d in inst],
+            [d["n"] for d in inst], [d["scheme"] for d in inst], [d["bc"] for d in inst])
+    b = adr.assemble_batch(*cols, field=cuda(np.concatenate(flds)), amp=0.1)
+    b.ilu0("fp32_factors")
+    b.autotune()
+    res = b.solve(1e-10, 2000)
+    xs = b.split(res.x)
+    order = sorted(range(len(inst)), key=lambda k: inst[k]["n"])
+    sample = [order[0], order[1], order[len(order) // 8]]
+    for k in sample:
+        d = inst[k]
+        P = oracle_problem(d["eps"], d["X"], d["Y"], d["n"], d["n"], d["scheme"], d["bc"], field=flds[k], amp=0.1)
+        ref = orc.bicgstab(P, orc.round_factors_f32(orc.ilu0(P)), tol=1e-10, maxit=2000)
+        say("  instance %d n %d: status %d/%d passes %d/%d" % (k, d["n"], res.status[k], ref.status,
+                                                              res.iters[k], ref.iters))
+        assert res.status[k] == ref.status
+        assert res.iters[k] == ref.iters
+        np.testing.assert_array_equal(res.hist_l2[k], ref.hist_l2)
+        assert equal(host(xs[k]), ref.x)
+
+
 @pytest.mark.parametrize("rows", [15, 31])
 @pytest.mark.parametrize("precision", ["fp32_factors", "fp32_sweeps"])
 def test_mixed_precision_precond_bitwise(adr, rows, precision):
