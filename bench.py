@@ -212,6 +212,43 @@ def run_warmstart(args):
     wall = time.perf_counter() - t0
     s = ev["summary"]
     k = max(s["single_instances"], 1)
+    # network throughput on the matrix cores: inference and one training step
+    # of a batch of 64 instances (nominal FLOPs of the six 3x3 layers with the
+    # channel padding the kernels compute: 32 in, 32 out, last layer 16 out)
+    H = n + 2
+    B = 64
+    xin = torch.zeros((B, H, H, 32), dtype=torch.bfloat16, device="cuda")
+    xin[..., :9] = torch.randn((B, H, H, 9), device="cuda").to(torch.bfloat16)
+    u = torch.empty((B, H, H), dtype=torch.float32, device="cuda")
+    tgt = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
+    fwd_flop = 2.0 * B * H * H * 9 * 32 * (5 * 32 + 16)
+    stream = torch.cuda.current_stream()
+    net.forward(xin, out=u)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        net.forward(xin, out=u)
+    e1.record(stream)
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+    # training: forward + input gradients of layers 2..6 + weight gradients of all six
+    step_flop = fwd_flop + 2.0 * B * H * H * 9 * 32 * (5 * 32) + fwd_flop
+    net2 = adr.WarmStartNet(H, H, B)
+    net2.set_params(np.load(tw.DEFAULT_WEIGHTS, allow_pickle=False))
+    net2.train_step(xin, tgt, lr=0.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(5):
+        net2.train_step(xin, tgt, lr=0.0)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t1) * 1e3 / 5
+    mfma = dict(bound="mfma", kernel="k_conv (6-layer forward, batch 64, 258x258)",
+                achieved=round(fwd_flop / (fwd_ms * 1e-3) / 1e12, 1), peak=2500.0, unit="TFLOP/s",
+                frac=round(fwd_flop / (fwd_ms * 1e-3) / 1e12 / 2500.0, 4), traffic=None,
+                forward_ms=round(fwd_ms, 3), train_step_ms=round(step_ms, 3),
+                train_step_tflops=round(step_flop / (step_ms * 1e-3) / 1e12, 1))
+    log("  network: forward %.2f ms (%.0f TFLOP/s), training step %.2f ms" % (fwd_ms, mfma["achieved"], step_ms))
     out = {
         "metric": "time to rel-resid 1e-10 per instance from the learned guess (single-instance solves)",
         "value": round(s["single_warm_ms"] / k / 1e3, 5), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -224,6 +261,7 @@ def run_warmstart(args):
                    "weights": os.path.relpath(tw.DEFAULT_WEIGHTS, ROOT), "tol": args.tol},
         "zero_guess_s": round(s["single_zero_ms"] / k / 1e3, 5),
         "summary": s,
+        "roofline": mfma,
     }
     print(json.dumps(out), flush=True)
 
