@@ -441,7 +441,6 @@ adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X,
   *out = nullptr;
   if (count < 1) return fail(ADR_ERR_ARG, "count must be >= 1 (got %d)", count);
   if (!eps || !X || !Y || !nx || !ny || !scheme || !bc) return fail(ADR_ERR_ARG, "NULL parameter array");
-  int64_t total = 0;
   for (int k = 0; k < count; ++k) {
     if (!(eps[k] > 0.0) || !std::isfinite(eps[k]))
       return fail(ADR_ERR_ARG, "instance %d: eps must be a finite number > 0 (got %g)", k, eps[k]);
@@ -455,7 +454,6 @@ adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X,
       return fail(ADR_ERR_ARG, "instance %d: unknown bc %d", k, bc[k]);
     if ((int64_t)nx[k] * ny[k] > (int64_t)0x7fffffff)
       return fail(ADR_ERR_ARG, "instance %d: nx*ny must be < 2^31", k);
-    total += (int64_t)nx[k] * ny[k];
   }
   if (field_dev && !std::isfinite(amp)) return fail(ADR_ERR_ARG, "amp must be finite");
 
