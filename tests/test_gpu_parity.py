@@ -38,7 +38,7 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-SHAPES = [(64, 64), (37, 53), (1, 20), (20, 1), (130, 67), (33, 96)]
+SHAPES = [(64, 64), (37, 53), (1, 20), (20, 1), (1, 1), (130, 67), (33, 96)]
 
 
 def oracle_problem(eps, X, Y, nx, ny, scheme, bc, field=None, amp=0.0):
@@ -160,6 +160,20 @@ def test_solve_parity(adr, rows, nx, ny, scheme, bc, eps, X, Y):
     assert abs(res.iters - ref.iters) <= 2
     assert res.half_step == ref.half_step or abs(res.iters - ref.iters) > 0
     assert maxrel(host(res.x), ref.x) <= 1e-9
+
+
+@pytest.mark.parametrize("nx,ny,scheme,bc", [(1, 1, 0, 0), (1, 1, 1, 1), (1, 300, 0, 1), (300, 1, 1, 0),
+                                              (1, 70, 1, 0), (70, 1, 0, 1)])
+def test_one_dimensional_grids_solve_in_one_pass(adr, nx, ny, scheme, bc):
+    """With one row or one column the 5-point matrix is tridiagonal (or 1x1),
+    ILU(0) is its exact LU factorisation, and BiCGSTAB stops in the first pass
+    (on the s test) on the GPU as in the oracle."""
+    say("1-D solve", nx, ny, scheme, bc)
+    prob, res, P, ref = solve_both(adr, 0.2, 1.0, 1.0, nx, ny, scheme, bc)
+    assert ref.status == orc.OK and ref.iters == 1
+    assert res.status == adr.OK and res.iters == ref.iters and res.half_step == ref.half_step
+    assert maxrel(host(res.x), ref.x) <= 1e-9
+    assert res.true_relres < 1e-11
 
 
 def test_solve_status_parity(adr):
