@@ -30,14 +30,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes per unknown (FP64): what each kernel must move with
-# perfect reuse of neighbours
-BYTES = {
-    "lsweep": 32,    # q, lw, ls in; y out
-    "usweep": 40,    # y, E, N, invd in; z out
-    "spmv_dot": 64,  # x, S, W, C, E, N, r^ in; v out
-    "iteration": 392,
-}
+
+
+def kernel_bytes(precision="fp64", tables=True):
+    """Algorithmic bytes per unknown of each kernel: what it must move with
+    perfect reuse of neighbours.  With stencil tables the iteration reads S,
+    W, E, N from per-column / per-row tables (a few KB) instead of four full
+    diagonals; "dia" gives the figures of the plain five-diagonal reads."""
+    f = 4 if precision == "fp32_factors" else 8          # bytes of a stored factor
+    if tables:
+        ls = 8 + 8 + 8 if precision == "fp64" else 8 + 2 * f + 8   # q, invd (FP64) | q, lw, ls; y out
+        us = 8 + f + 8                                              # y, invd in; z out
+        sp = 8 + 8 + 8 + 8                                          # x, C, r^ in; v out
+    else:
+        ls = 8 + 2 * f + 8                                          # q, lw, ls in; y out
+        us = 8 + 3 * f + 8                                          # y, E, N, invd in; z out
+        sp = 8 + 40 + 8 + 8                                         # x, S, W, C, E, N, r^ in; v out
+    # pass: p update 32, two L and two U sweeps, two stencil products with a
+    # dot, s update 24, x / r update 64
+    return {"lsweep": ls, "usweep": us, "spmv_dot": sp, "iteration": 32 + 2 * (ls + us) + 2 * sp + 24 + 64,
+            "spmv": 56}   # the stand-alone stencil product reads the five diagonals
+
+
+BYTES = kernel_bytes("fp64", tables=True)
+BYTES_DIA = kernel_bytes("fp64", tables=False)
 
 
 def parse():
@@ -179,7 +195,7 @@ def run_batch(args):
                    "total_unknowns": int(sum(N)), "seed": 1308},
         "statuses": counts,
         "unknown_passes_per_s": round(work / batch_s, 1),
-        "hbm_gbs_algorithmic": round(BYTES["iteration"] * work / batch_s / 1e9, 1),
+        "hbm_gbs_algorithmic": round(kernel_bytes(args.batch_precision)["iteration"] * work / batch_s / 1e9, 1),
         "sequential": {"solve_s": round(seq_s, 3), "instances_timed": len(sample),
                        "extrapolated": len(sample) != len(inst),
                        "speedup_batched": round(seq_s / batch_s, 2) if batch_s > 0 else None,
@@ -284,7 +300,7 @@ def run_large(args):
     N = n * n
     X, Y, eps = 2.0, 1.0, 1e-3
     solves, windows = {}, {}
-    bytes_pass = {"fp32_factors": 352, "fp64": 392}
+    bytes_pass = {p: kernel_bytes(p)["iteration"] for p in ("fp32_factors", "fp64")}
     for sc in ("upwind", "centered"):
         prob = adr.assemble(eps, X, Y, n, n, sc, "dirichlet")
         try:
@@ -323,8 +339,7 @@ def run_large(args):
     q = torch.randn(N, dtype=torch.float64, device="cuda")
     y = torch.empty_like(q)
     z = torch.empty_like(q)
-    for prec, kb in (("fp32_factors", {"lsweep": 24, "usweep": 28, "spmv": 56}),
-                     ("fp64", {"lsweep": 32, "usweep": 40, "spmv": 56})):
+    for prec, kb in (("fp32_factors", kernel_bytes("fp32_factors")), ("fp64", kernel_bytes("fp64"))):
         prob = adr.assemble(eps, X, Y, n, n, "centered", "dirichlet")
         prob.ilu0(prec)
         kernels[prec] = {}
@@ -425,6 +440,7 @@ def main():
     N = n * n
     stream = torch.cuda.current_stream()
     schemes = ("upwind", "centered")
+    tables_used = []
 
     def hot_path(scheme, bc="dirichlet", maxit=args.maxit):
         prob = adr.assemble(args.eps, 1.0, 1.0, n, n, scheme, bc)
@@ -432,6 +448,7 @@ def main():
             prob.set_sweep_rows(args.rows)
         prob.ilu0(args.precision)
         res = prob.solve(tol=args.tol, maxit=maxit)
+        tables_used.append(prob.stencil_tables)
         return prob, res
 
     log("warmup: %d step(s)" % args.warmup)
@@ -456,7 +473,10 @@ def main():
     iters = {sc: [s["iters"] for s in solves if s["scheme"] == sc] for sc in schemes}
     mean_iters = float(np.mean([s["iters"] for s in solves]))
     ms_per_iter = float(np.mean([s["solve_ms"] / max(s["iters"], 1) for s in solves]))
+    if not all(tables_used):
+        raise RuntimeError("the solves did not use the stencil tables; the byte model below assumes them")
     algo_gbs = BYTES["iteration"] * N / (ms_per_iter * 1e-3) / 1e9
+    dia_gbs = BYTES_DIA["iteration"] * N / (ms_per_iter * 1e-3) / 1e9
 
     # ---- per-kernel timing with HIP events on the library's stream ----
     log("kernel timing")
@@ -477,7 +497,7 @@ def main():
         e1.record(stream)
         e1.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
-        b = {"lsweep": 32, "usweep": 40, "spmv": 56}[name] * N
+        b = BYTES[name] * N
         kern[name] = dict(avg_us=us, algorithmic_bytes=b, gbs=b / (us * 1e-6) / 1e9)
         log("  %s: %.1f us  %.0f GB/s" % (name, us, kern[name]["gbs"]))
     dom = max(("lsweep", "usweep"), key=lambda k: kern[k]["avg_us"])
@@ -561,8 +581,12 @@ def main():
                    "sweep_rows": args.rows or "auto"},
         "iters": iters,
         "ms_per_iter": round(ms_per_iter, 4),
+        "bytes_per_unknown_per_pass": BYTES["iteration"],
         "hbm_gbs_algorithmic": round(algo_gbs, 1),
         "hbm_frac_algorithmic": round(algo_gbs / PEAK_HBM_GBS, 4),
+        # what a plain five-diagonal implementation would have to move per
+        # second to keep this pace (392 B per unknown per pass)
+        "hbm_gbs_dia_equivalent": round(dia_gbs, 1),
         "kernels": {k: {kk: round(vv, 2) for kk, vv in v.items()} for k, v in kern.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -245,6 +245,22 @@ size_t adr_device_bytes(const adr_problem *p);
  * or 0 to pick automatically.  For tuning and tests. */
 adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
 
+/* Stencil tables.  The off-diagonals of the operator of Section 4 are
+ * separable: W and E depend only on the column, S and N only on the row
+ * (a = a(x), b = b(y), couplings to boundary nodes zero).  After
+ * adr_assemble / adr_batch_assemble / adr_set_dia the library copies them into
+ * per-instance column and row tables and checks every point against them bit
+ * for bit; when all match, the iteration reads the tables instead of the
+ * four off-diagonals (the stencil products then read the diagonal C only, the
+ * FP64 L sweep forms lw = W invd_w and ls = S invd_s from invd as the
+ * factorisation does, and the U sweep takes E and N from the tables), which
+ * changes no result bit.  adr_use_stencil_tables(p, 0) makes the iteration
+ * read the full diagonals; 1 (the default) allows the tables.
+ * adr_stencil_tables returns 1 if the next solve reads the tables, 0 if it
+ * reads the diagonals (also for p == NULL). */
+adr_status adr_use_stencil_tables(adr_problem *p, int32_t enable);
+int32_t adr_stencil_tables(const adr_problem *p);
+
 const char *adr_status_str(int32_t status);
 /* Message of the last call error on this thread ("" if none). */
 const char *adr_last_error(void);

@@ -167,6 +167,16 @@ class Problem:
     def set_sweep_rows(self, rows):
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
 
+    def use_stencil_tables(self, enable=True):
+        """Allow (default) or forbid reading S, W, E, N from the separable
+        stencil tables instead of the full diagonals (no result changes)."""
+        _lib.check(_lib.load().adr_use_stencil_tables(self._h, 1 if enable else 0))
+
+    @property
+    def stencil_tables(self):
+        """True if the next solve reads the stencil tables."""
+        return bool(_lib.load().adr_stencil_tables(self._h))
+
     @property
     def device_bytes(self):
         return int(_lib.load().adr_device_bytes(self._h))
@@ -247,6 +257,13 @@ class Batch:
 
     def set_sweep_rows(self, rows):
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
+
+    def use_stencil_tables(self, enable=True):
+        _lib.check(_lib.load().adr_use_stencil_tables(self._h, 1 if enable else 0))
+
+    @property
+    def stencil_tables(self):
+        return bool(_lib.load().adr_stencil_tables(self._h))
 
     def split(self, x):
         """Per-instance views of a batched vector."""

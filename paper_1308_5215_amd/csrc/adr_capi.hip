@@ -120,6 +120,12 @@ struct adr_problem {
   // matrix (batched)
   double *S = nullptr, *W = nullptr, *C = nullptr, *E = nullptr, *N = nullptr, *rhs = nullptr;
   double *F = nullptr;         // forcing f per unknown (input of the warm-start network)
+  // stencil tables (separable S, W, E, N; verified against the diagonals)
+  double *tab = nullptr;
+  unsigned *tab_bad = nullptr;
+  int64_t tab_len = 0;
+  int has_tab = 0;    // tables match every point
+  int tab_on = 1;     // the caller allows them (adr_use_stencil_tables)
   // factors
   double *lw = nullptr, *ls = nullptr, *invd = nullptr;
   float *lw32 = nullptr, *ls32 = nullptr, *invd32 = nullptr, *E32 = nullptr, *N32 = nullptr;
@@ -146,10 +152,11 @@ struct adr_problem {
   hipGraphExec_t gexec = nullptr;
   double *g_x = nullptr;
   double g_tol = -1;
-  int g_maxit = -1, g_prec = -1, g_rows = -1, g_K = 0;
+  int g_maxit = -1, g_prec = -1, g_rows = -1, g_K = 0, g_tab = -1;
 
   SweepSync sync() const { return SweepSync{ticket, handoff, err}; }
   Dia dia() const { return Dia{S, W, C, E, N}; }
+  const double *stencil_tab() const { return (has_tab && tab_on) ? tab : nullptr; }
   BatchGeom geom() const { return BatchGeom{d_inst, count, nblk, nstrips, rows}; }
 };
 
@@ -157,7 +164,7 @@ namespace {
 
 // (Re)build the instance table for strip height R and upload it.
 adr_status build_table(adr_problem *P, int R) {
-  int64_t off = 0, ho = 0;
+  int64_t off = 0, ho = 0, tabo = 0;
   int blk = 0, strip = 0;
   for (int k = 0; k < P->count; ++k) {
     Inst &I = P->inst[k];
@@ -174,12 +181,15 @@ adr_status build_table(adr_problem *P, int R) {
     I.ho_off = ho;
     I.fd = make_fastdiv((uint32_t)I.nx);
     I.pad = 0;
+    I.tab_off = tabo;
+    tabo += stencil_tab_len(I.nx, I.ny);
     off += I.n;
     blk += I.nblk;
     strip += I.nstrips;
     ho += (int64_t)I.nstrips * I.nx;
   }
   P->ntot = off;
+  P->tab_len = tabo;
   P->nblk = blk;
   P->nstrips = strip;
   P->rows = R;
@@ -238,6 +248,7 @@ adr_status ensure_iter_buffers(adr_problem *P, int maxit) {
 IterBufs iter_bufs(adr_problem *P, double *x, double tol, int maxit) {
   IterBufs B;
   B.A = P->dia();
+  B.tab = P->stencil_tab();
   B.b = P->rhs;
   B.x = x;
   B.r = P->r;
@@ -262,14 +273,18 @@ Factors32 f32_of(const adr_problem *P) { return Factors32{P->lw32, P->ls32, P->i
 // One BiCGSTAB pass over the batch (13 kernels).
 hipError_t enqueue_pass(adr_problem *P, const IterBufs &B, hipStream_t s) {
   const BatchGeom g = P->geom();
+  const Factors64 f64 = f64_of(P);
+  const Factors32 f32 = f32_of(P);
+  const double *tab = P->stencil_tab();
+  const int prec = P->precision;
   hipError_t e;
   if ((e = launch_pass_p(B, g, s)) != hipSuccess) return e;
-  if ((e = launch_lsweep(g, P->precision, f64_of(P), f32_of(P), P->p, P->y, P->sync(), P->st, s)) != hipSuccess) return e;
-  if ((e = launch_usweep(g, P->precision, P->dia(), f64_of(P), f32_of(P), P->y, P->ph, P->sync(), P->st, s)) != hipSuccess) return e;
+  if ((e = launch_lsweep(g, prec, f64, f32, tab, P->p, P->y, P->sync(), P->st, s)) != hipSuccess) return e;
+  if ((e = launch_usweep(g, prec, P->dia(), f64, f32, tab, P->y, P->ph, P->sync(), P->st, s)) != hipSuccess) return e;
   if ((e = launch_pass_v(B, g, s)) != hipSuccess) return e;
   if ((e = launch_pass_s(B, g, s)) != hipSuccess) return e;
-  if ((e = launch_lsweep(g, P->precision, f64_of(P), f32_of(P), P->s, P->y, P->sync(), P->st, s)) != hipSuccess) return e;
-  if ((e = launch_usweep(g, P->precision, P->dia(), f64_of(P), f32_of(P), P->y, P->z, P->sync(), P->st, s)) != hipSuccess) return e;
+  if ((e = launch_lsweep(g, prec, f64, f32, tab, P->s, P->y, P->sync(), P->st, s)) != hipSuccess) return e;
+  if ((e = launch_usweep(g, prec, P->dia(), f64, f32, tab, P->y, P->z, P->sync(), P->st, s)) != hipSuccess) return e;
   if ((e = launch_pass_t(B, g, s)) != hipSuccess) return e;
   return launch_pass_xr(B, g, s);
 }
@@ -362,6 +377,24 @@ adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double a
   return ADR_OK;
 }
 
+// Copy the stencil tables out of the diagonals and keep them only if every
+// point's S, W, E, N equals its table entry (always so for assembled
+// operators; a matrix given through adr_set_dia may not be separable).
+adr_status refresh_stencil_tables(adr_problem *P) {
+  P->has_tab = 0;
+  if (!P->tab) {
+    HIP_TRY(dalloc(&P->tab, (size_t)P->tab_len, P->bytes));
+    HIP_TRY(dalloc(&P->tab_bad, 1, P->bytes));
+  }
+  HIP_TRY(launch_fill_u32(P->tab_bad, 1, 0u, P->stream));
+  HIP_TRY(launch_stencil_tables(P->dia(), P->geom(), P->tab, P->tab_bad, P->stream));
+  unsigned bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, P->tab_bad, sizeof(unsigned), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  P->has_tab = bad == 0;
+  return ADR_OK;
+}
+
 adr_status ensure_feat_table(adr_problem *P) {
   if (P->d_feat) return ADR_OK;
   std::vector<FeatInst> fi((size_t)P->count);
@@ -416,7 +449,7 @@ void adr_destroy(adr_problem *P) {
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
   if (P->cap) (void)hipStreamDestroy(P->cap);
   double *dv[] = {P->S, P->W, P->C, P->E, P->N, P->rhs, P->F, P->lw, P->ls, P->invd, P->r, P->rh,
-                  P->p, P->v, P->s, P->t, P->ph, P->z, P->y, P->hist, P->scal};
+                  P->p, P->v, P->s, P->t, P->ph, P->z, P->y, P->hist, P->scal, P->tab};
   for (double *q : dv) dfree(q);
   float *fv[] = {P->lw32, P->ls32, P->invd32, P->E32, P->N32};
   for (float *q : fv) dfree(q);
@@ -428,6 +461,7 @@ void adr_destroy(adr_problem *P) {
   dfree(P->err);
   dfree(P->d_inst);
   dfree(P->d_feat);
+  dfree(P->tab_bad);
   if (P->h_st) (void)hipHostFree(P->h_st);
   delete P;
 }
@@ -487,6 +521,8 @@ adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X,
     st = assemble_one(P, k, field_dev, amp);
     if (st != ADR_OK) return bail(st);
   }
+  st = refresh_stencil_tables(P);
+  if (st != ADR_OK) return bail(st);
   *out = P;
   return ADR_OK;
 }
@@ -533,7 +569,7 @@ adr_status adr_set_dia(adr_problem *P, const double *S, const double *W, const d
     HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)P->ntot * sizeof(double), hipMemcpyHostToDevice, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   P->factored = 0;
-  return ADR_OK;
+  return refresh_stencil_tables(P);
 }
 
 adr_status adr_get_factors(const adr_problem *P, double *lw, double *ls, double *invd) {
@@ -557,6 +593,16 @@ adr_status adr_set_sweep_rows(adr_problem *P, int32_t rows) {
 }
 
 size_t adr_device_bytes(const adr_problem *P) { return P ? P->bytes : 0; }
+
+adr_status adr_use_stencil_tables(adr_problem *P, int32_t enable) {
+  g_last_error.clear();
+  if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
+  if (enable != 0 && enable != 1) return fail(ADR_ERR_ARG, "enable must be 0 or 1 (got %d)", enable);
+  P->tab_on = enable;
+  return ADR_OK;
+}
+
+int32_t adr_stencil_tables(const adr_problem *P) { return (P && P->stencil_tab()) ? 1 : 0; }
 
 adr_status adr_batch_ilu0(adr_problem *P, int32_t precision, int64_t *bad_index) {
   g_last_error.clear();
@@ -620,7 +666,7 @@ adr_status adr_lsolve(adr_problem *P, const double *q, double *y) {
   g_last_error.clear();
   if (!P || !q || !y) return fail(ADR_ERR_ARG, "NULL argument");
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
-  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), q, y, P->sync(), nullptr, P->stream));
+  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->stencil_tab(), q, y, P->sync(), nullptr, P->stream));
   return check_device_fault(P);
 }
 
@@ -628,7 +674,7 @@ adr_status adr_usolve(adr_problem *P, const double *y, double *z) {
   g_last_error.clear();
   if (!P || !y || !z) return fail(ADR_ERR_ARG, "NULL argument");
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
-  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), y, z, P->sync(), nullptr,
+  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->stencil_tab(), y, z, P->sync(), nullptr,
                         P->stream));
   return check_device_fault(P);
 }
@@ -639,8 +685,8 @@ adr_status adr_precond(adr_problem *P, const double *q, double *z) {
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
   adr_status st = ensure_iter_buffers(P, 0);
   if (st != ADR_OK) return st;
-  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), q, P->y, P->sync(), nullptr, P->stream));
-  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->y, z, P->sync(), nullptr,
+  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->stencil_tab(), q, P->y, P->sync(), nullptr, P->stream));
+  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->stencil_tab(), P->y, z, P->sync(), nullptr,
                         P->stream));
   return check_device_fault(P);
 }
@@ -664,9 +710,9 @@ adr_status adr_autotune(adr_problem *P, int32_t *rows_chosen, double *ms_per_app
     float ms = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
       HIP_TRY(hipEventRecord(e0, P->stream));
-      HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->rhs, P->y, P->sync(), nullptr,
+      HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->stencil_tab(), P->rhs, P->y, P->sync(), nullptr,
                             P->stream));
-      HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->y, P->z, P->sync(), nullptr,
+      HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->stencil_tab(), P->y, P->z, P->sync(), nullptr,
                             P->stream));
       HIP_TRY(hipEventRecord(e1, P->stream));
       HIP_TRY(hipEventSynchronize(e1));
@@ -738,7 +784,7 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
   int K = P->ntot >= (1 << 22) ? 4 : (P->ntot >= (1 << 18) ? 8 : 16);
   if (K > maxit && maxit > 0) K = maxit;
   if (!P->gexec || P->g_x != x || P->g_tol != tol || P->g_maxit != maxit || P->g_prec != P->precision ||
-      P->g_rows != P->rows || P->g_K != K) {
+      P->g_rows != P->rows || P->g_K != K || P->g_tab != (P->stencil_tab() != nullptr)) {
     st = build_graph(P, B, K);
     if (st != ADR_OK) return st;
     P->g_x = x;
@@ -746,6 +792,7 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
     P->g_maxit = maxit;
     P->g_prec = P->precision;
     P->g_rows = P->rows;
+    P->g_tab = P->stencil_tab() != nullptr;
   }
   auto all_done = [&]() {
     for (int k = 0; k < P->count; ++k)

@@ -167,6 +167,24 @@ __device__ __forceinline__ double spmv_point(const Dia &A, const double *__restr
   return t;
 }
 
+// The same product with S, W, E, N read from the instance's stencil tables
+// (tab = its Wc, Ec, Sr, Nr): the stored coefficients, so the same bits.
+__device__ __forceinline__ double spmv_point_tab(const double *__restrict__ C, const double *__restrict__ tab,
+                                                 const double *__restrict__ x, int k, int i, int j, int nx,
+                                                 int ny) {
+  const double *Wc = tab, *Ec = tab + nx, *Sr = tab + 2 * nx, *Nr = Sr + ny;
+  const double xs = (j > 0) ? x[k - nx] : 0.0;
+  const double xw = (i > 0) ? x[k - 1] : 0.0;
+  const double xe = (i < nx - 1) ? x[k + 1] : 0.0;
+  const double xn = (j < ny - 1) ? x[k + nx] : 0.0;
+  double t = C[k] * x[k];
+  t = fma(Sr[j], xs, t);
+  t = fma(Wc[i], xw, t);
+  t = fma(Ec[i], xe, t);
+  t = fma(Nr[j], xn, t);
+  return t;
+}
+
 __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
 
 __device__ __forceinline__ int find_block_inst(const Inst *inst, int ninst, int b) {

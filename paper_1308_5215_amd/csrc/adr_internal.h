@@ -56,7 +56,19 @@ struct Inst {
   int64_t ho_off;           // offset in the hand-off buffer (64-bit words)
   FastDiv fd;               // division by nx
   int32_t pad;
+  int64_t tab_off;          // offset of the instance's stencil tables (below)
 };
+
+// Stencil tables.  The off-diagonals of the assembled operator are separable:
+// W and E depend on the column i only, S and N on the row j only (Section 4:
+// a = a(x), b = b(y), and the couplings to boundary nodes are zero in every
+// row or column).  Instance k keeps, at tab + inst[k].tab_off,
+//   Wc[nx], Ec[nx], Sr[ny], Nr[ny]   with W(i,j) = Wc[i], E(i,j) = Ec[i],
+//                                         S(i,j) = Sr[j], N(i,j) = Nr[j],
+// copied out of the diagonals themselves and verified against every point,
+// so reading a table gives the stored coefficient bit for bit.  Kernels given
+// tab == nullptr read the full diagonals.
+inline int64_t stencil_tab_len(int nx, int ny) { return 2 * ((int64_t)nx + ny); }
 
 // Launch geometry of a batch.
 struct BatchGeom {
@@ -110,6 +122,7 @@ hipError_t launch_dot(const double *x, const double *y, const Stream1D &g, doubl
 // BiCGSTAB step kernels (batched).
 struct IterBufs {
   Dia A;
+  const double *tab;   // stencil tables, or nullptr: read S, W, E, N from A
   const double *b;
   double *x, *r, *rh, *p, *v, *s, *t, *ph, *z;
   double2 *partials;   // [4][total blocks]
@@ -136,12 +149,20 @@ struct Factors32 {
 hipError_t launch_ilu0(const Dia &A, const BatchGeom &g, Factors64 f64, Factors32 f32,
                        const SweepSync &sync, int64_t *bad, hipStream_t s);
 // precision: 0 = FP64 factors, 1 = FP32 factors/FP64 arithmetic, 2 = FP32 arithmetic
+// tab: stencil tables or nullptr.  With tables the FP64-factor L sweep forms
+// lw = W invd_w and ls = S invd_s from invd (as the factorisation does) and
+// the U sweep takes E and N from the tables.
 hipError_t launch_lsweep(const BatchGeom &g, int precision, const Factors64 &f64,
-                         const Factors32 &f32, const double *q, double *y, const SweepSync &sync,
-                         const SolveState *st, hipStream_t s);
+                         const Factors32 &f32, const double *tab, const double *q, double *y,
+                         const SweepSync &sync, const SolveState *st, hipStream_t s);
 hipError_t launch_usweep(const BatchGeom &g, int precision, const Dia &A, const Factors64 &f64,
-                         const Factors32 &f32, const double *y, double *z, const SweepSync &sync,
-                         const SolveState *st, hipStream_t s);
+                         const Factors32 &f32, const double *tab, const double *y, double *z,
+                         const SweepSync &sync, const SolveState *st, hipStream_t s);
+// Copy the stencil tables of every instance out of the diagonals, then count
+// the points whose S, W, E or N differ from their table entry (bitwise) into
+// *mismatch (device, cleared by the caller).
+hipError_t launch_stencil_tables(const Dia &A, const BatchGeom &g, double *tab, unsigned *mismatch,
+                                 hipStream_t s);
 
 // ---- error text shared by every C entry point (adr_capi.hip) ----
 int set_error(int st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));

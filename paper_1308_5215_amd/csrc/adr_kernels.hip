@@ -279,6 +279,42 @@ hipError_t launch_init(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Stencil tables: row 0 gives Wc and Ec, column 0 gives Sr and Nr; the check
+// then compares every point's S, W, E, N with its table entry bit for bit.
+__global__ __launch_bounds__(BLK) void k_tab_copy(Dia D, BatchGeom g, double *tab) {
+  ADR_BATCH_BLOCK(g);
+  double *Wc = tab + I.tab_off, *Ec = Wc + I.nx, *Sr = Ec + I.nx, *Nr = Sr + I.ny;
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
+    if (j == 0) {
+      Wc[i] = D.W[o + k];
+      Ec[i] = D.E[o + k];
+    }
+    if (i == 0) {
+      Sr[j] = D.S[o + k];
+      Nr[j] = D.N[o + k];
+    }
+  }
+}
+__global__ __launch_bounds__(BLK) void k_tab_check(Dia D, BatchGeom g, const double *tab, unsigned *mismatch) {
+  ADR_BATCH_BLOCK(g);
+  const double *Wc = tab + I.tab_off, *Ec = Wc + I.nx, *Sr = Ec + I.nx, *Nr = Sr + I.ny;
+  auto bits = [](double v) { return (unsigned long long)__double_as_longlong(v); };
+  unsigned bad = 0;
+  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
+    const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
+    bad += (bits(D.W[o + k]) != bits(Wc[i])) + (bits(D.E[o + k]) != bits(Ec[i])) +
+           (bits(D.S[o + k]) != bits(Sr[j])) + (bits(D.N[o + k]) != bits(Nr[j]));
+  }
+  if (bad) atomicAdd(mismatch, bad);
+}
+hipError_t launch_stencil_tables(const Dia &A, const BatchGeom &g, double *tab, unsigned *mismatch,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_tab_copy, dim3(g.nblk), dim3(BLK), 0, s, A, g, tab);
+  hipLaunchKernelGGL(k_tab_check, dim3(g.nblk), dim3(BLK), 0, s, A, g, (const double *)tab, mismatch);
+  return hipGetLastError();
+}
+
 // p = r (first pass) or p = fma(beta, fma(-omega, v, p), r).
 __global__ __launch_bounds__(BLK) void k_pass_p(IterBufs B, BatchGeom g) {
   ADR_BATCH_BLOCK(g);
@@ -298,17 +334,27 @@ hipError_t launch_pass_p(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Stencil product at point k of an instance: from the stencil tables (TAB)
+// or from the full diagonals.
+template <bool TAB>
+__device__ __forceinline__ double stencil_point(const Dia &A, const double *tab, const double *x, int k, int i,
+                                                int j, int nx, int ny) {
+  return TAB ? spmv_point_tab(A.C, tab, x, k, i, j, nx, ny) : spmv_point(A, x, k, i, j, nx, ny);
+}
+
 // v = A p^; partial r^.v; finalize alpha = rho / (r^.v).
+template <bool TAB>
 __global__ __launch_bounds__(BLK) void k_pass_v(IterBufs B, BatchGeom g) {
   ADR_BATCH_BLOCK(g);
   if (B.st[ii].phase != RUNNING) return;
   Dia A{B.A.S + o, B.A.W + o, B.A.C + o, B.A.E + o, B.A.N + o};
+  const double *tab = TAB ? B.tab + I.tab_off : nullptr;
   const double *ph = B.ph + o, *rh = B.rh + o;
   double *v = B.v + o;
   dd acc[1] = {dd{0.0, 0.0}};
   for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
     const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
-    const double vk = spmv_point(A, ph, k, i, j, I.nx, I.ny);
+    const double vk = stencil_point<TAB>(A, tab, ph, k, i, j, I.nx, I.ny);
     v[k] = vk;
     acc[0] = dd_add(acc[0], dd_prod(rh[k], vk));
   }
@@ -325,7 +371,8 @@ __global__ __launch_bounds__(BLK) void k_pass_v_fin(IterBufs B, BatchGeom g) {
   if (!finite(S.alpha)) { S.status = 5; S.phase = DONE; }
 }
 hipError_t launch_pass_v(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
-  hipLaunchKernelGGL(k_pass_v, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  if (B.tab) hipLaunchKernelGGL(k_pass_v<true>, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  else hipLaunchKernelGGL(k_pass_v<false>, dim3(g.nblk), dim3(BLK), 0, s, B, g);
   hipLaunchKernelGGL(k_pass_v_fin, dim3(g.ninst), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }
@@ -373,16 +420,18 @@ hipError_t launch_pass_s(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
 }
 
 // t = A z; partials t.s, t.t; finalize omega = (t.s)/(t.t).
+template <bool TAB>
 __global__ __launch_bounds__(BLK) void k_pass_t(IterBufs B, BatchGeom g) {
   ADR_BATCH_BLOCK(g);
   if (B.st[ii].phase != RUNNING) return;
   Dia A{B.A.S + o, B.A.W + o, B.A.C + o, B.A.E + o, B.A.N + o};
+  const double *tab = TAB ? B.tab + I.tab_off : nullptr;
   const double *z = B.z + o, *sv = B.s + o;
   double *t = B.t + o;
   dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
   for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
     const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
-    const double tk = spmv_point(A, z, k, i, j, I.nx, I.ny);
+    const double tk = stencil_point<TAB>(A, tab, z, k, i, j, I.nx, I.ny);
     t[k] = tk;
     acc[0] = dd_add(acc[0], dd_prod(tk, sv[k]));
     acc[1] = dd_add(acc[1], dd_prod(tk, tk));
@@ -401,7 +450,8 @@ __global__ __launch_bounds__(BLK) void k_pass_t_fin(IterBufs B, BatchGeom g) {
   if (!finite(S.omega)) { S.status = 5; S.phase = DONE; }
 }
 hipError_t launch_pass_t(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
-  hipLaunchKernelGGL(k_pass_t, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  if (B.tab) hipLaunchKernelGGL(k_pass_t<true>, dim3(g.nblk), dim3(BLK), 0, s, B, g);
+  else hipLaunchKernelGGL(k_pass_t<false>, dim3(g.nblk), dim3(BLK), 0, s, B, g);
   hipLaunchKernelGGL(k_pass_t_fin, dim3(g.ninst), dim3(BLK), 0, s, B, g);
   return hipGetLastError();
 }

@@ -109,11 +109,16 @@ __device__ __forceinline__ void strip_finish(const SweepSync &sy, int nstrips) {
 //   OP 0 (L): y = fma(-ls, y_s, fma(-lw, y_w, q))          inputs q, lw, ls
 //   OP 1 (U): z = fma(-N, z_n, fma(-E, z_e, y)) * invd     inputs y, E, N, invd
 // PREC 0: factors FP64; 1: factors FP32, arithmetic FP64; 2: arithmetic FP32.
+// TAB: S, W, E, N come from the stencil tables: the U sweep reads E and N
+// there, the FP64 L sweep forms lw = W invd_w and ls = S invd_s from invd in
+// the factorisation's own operation order (one array instead of two).
 // ---------------------------------------------------------------------------
 struct SweepParams {
   BatchGeom g;
   const double *v;      // q (L) or y (U), batched
   const void *f1, *f2, *f3;   // lw, ls (L) or E, N, invd (U); double or float per PREC
+                              // (TAB: L uses only f3 = invd, U only f3)
+  const double *tab;    // stencil tables (TAB)
   double *out;
   SweepSync sync;
   const SolveState *st;  // per-instance state (null: always run)
@@ -177,8 +182,9 @@ struct SweepShape {
 
 }  // namespace
 
-template <int R, int OP, int PREC>
+template <int R, int OP, int PREC, bool TAB>
 __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
+  static_assert(!TAB || OP == 1 || PREC == 0, "the L sweep forms its factors from tables only in FP64");
   using TF = typename std::conditional<PREC == 0, double, float>::type;
   using CT = typename std::conditional<PREC == 2, float, double>::type;
   constexpr int NIN = (OP == 0) ? 3 : 4;
@@ -232,6 +238,8 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   if (wave >= 3) {
     // ------------------------------------------------------------ loaders
     const TF *f1 = (const TF *)p.f1 + I.off, *f2 = (const TF *)p.f2 + I.off, *f3 = (const TF *)p.f3 + I.off;
+    const double *Wc = TAB ? p.tab + I.tab_off : nullptr;
+    const double *Ec = Wc + nx, *Sr = Wc + 2 * nx, *Nr = Sr + ny;
     for (int c = wave - 3; c < nchunks; c += NLD) {
       // every load of the tile is issued before any is used (points outside
       // the strip load element 0 and are zeroed afterwards), so the loads
@@ -239,17 +247,42 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
       double bv[NP];
       TF bf[NIN - 1][NP];
       bool okq[NP];
+      double iw[TAB && OP == 0 ? NP : 1], is[TAB && OP == 0 ? NP : 1];   // invd of the x- and y-predecessor
+      int fi[TAB && OP == 0 ? NP : 1], fj[TAB && OP == 0 ? NP : 1];
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const int l = 1 + q * RPP + lr;
         const int co = c * W + lc - l;
         const bool ok = (l <= rows) && (co >= 0) && (co < nx);
-        const size_t k = ok ? (size_t)grow(l) * nx + gcol(co) : 0;
+        const int gi = ok ? gcol(co) : 0, gj = ok ? grow(l) : 0;
+        const size_t k = (size_t)gj * nx + gi;
         okq[q] = ok;
         bv[q] = vin[k];
-        bf[0][q] = f1[k];
-        bf[1][q] = f2[k];
-        if (NIN == 4) bf[NIN - 2][q] = f3[k];
+        if (TAB && OP == 0) {
+          // lw = W(i) invd(k-1) for i > 0, ls = S(j) invd(k-nx) for j > 0, else 0
+          const double *invd = (const double *)f3;
+          iw[q] = invd[gi > 0 ? k - 1 : k];
+          is[q] = invd[gj > 0 ? k - nx : k];
+          bf[0][q] = (TF)Wc[gi];
+          bf[1][q] = (TF)Sr[gj];
+          fi[q] = gi;
+          fj[q] = gj;
+        } else if (TAB) {
+          bf[0][q] = (TF)Ec[gi];
+          bf[1][q] = (TF)Nr[gj];
+          bf[NIN - 2][q] = f3[k];
+        } else {
+          bf[0][q] = f1[k];
+          bf[1][q] = f2[k];
+          if (NIN == 4) bf[NIN - 2][q] = f3[k];
+        }
+      }
+      if (TAB && OP == 0) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          bf[0][q] = fi[q] > 0 ? (TF)((double)bf[0][q] * iw[q]) : (TF)0;
+          bf[1][q] = fj[q] > 0 ? (TF)((double)bf[1][q] * is[q]) : (TF)0;
+        }
       }
       lds_wait_ge(&s_computed, c - NC + 1);   // ring slot free
       const int sl = c % NC;
@@ -548,54 +581,58 @@ hipError_t launch_ilu0(const Dia &A, const BatchGeom &g, Factors64 f64, Factors3
   return hipGetLastError();
 }
 
-template <int OP, int PREC>
+template <int OP, int PREC, bool TAB>
 static hipError_t launch_sweep_t(const SweepParams &p, hipStream_t s) {
   switch (p.g.rows) {
-    case 15: hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
-    case 31: hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
+    case 15: hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC, TAB>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
+    case 31: hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_lsweep(const BatchGeom &g, int precision, const Factors64 &f64, const Factors32 &f32,
-                         const double *q, double *y, const SweepSync &sync, const SolveState *st,
-                         hipStream_t s) {
+                         const double *tab, const double *q, double *y, const SweepSync &sync,
+                         const SolveState *st, hipStream_t s) {
   SweepParams p{};
   p.g = g;
   p.v = q;
   p.out = y;
   p.sync = sync;
   p.st = st;
+  p.tab = tab;
   if (precision == 0) {
     p.f1 = f64.lw;
     p.f2 = f64.ls;
-    return launch_sweep_t<0, 0>(p, s);
+    p.f3 = f64.invd;
+    return tab ? launch_sweep_t<0, 0, true>(p, s) : launch_sweep_t<0, 0, false>(p, s);
   }
   p.f1 = f32.lw;
   p.f2 = f32.ls;
-  return precision == 1 ? launch_sweep_t<0, 1>(p, s) : launch_sweep_t<0, 2>(p, s);
+  return precision == 1 ? launch_sweep_t<0, 1, false>(p, s) : launch_sweep_t<0, 2, false>(p, s);
 }
 
 hipError_t launch_usweep(const BatchGeom &g, int precision, const Dia &A, const Factors64 &f64,
-                         const Factors32 &f32, const double *y, double *z, const SweepSync &sync,
-                         const SolveState *st, hipStream_t s) {
+                         const Factors32 &f32, const double *tab, const double *y, double *z,
+                         const SweepSync &sync, const SolveState *st, hipStream_t s) {
   SweepParams p{};
   p.g = g;
   p.v = y;
   p.out = z;
   p.sync = sync;
   p.st = st;
+  p.tab = tab;
   if (precision == 0) {
     p.f1 = A.E;
     p.f2 = A.N;
     p.f3 = f64.invd;
-    return launch_sweep_t<1, 0>(p, s);
+    return tab ? launch_sweep_t<1, 0, true>(p, s) : launch_sweep_t<1, 0, false>(p, s);
   }
   p.f1 = f32.E;
   p.f2 = f32.N;
   p.f3 = f32.invd;
-  return precision == 1 ? launch_sweep_t<1, 1>(p, s) : launch_sweep_t<1, 2>(p, s);
+  if (precision == 1) return tab ? launch_sweep_t<1, 1, true>(p, s) : launch_sweep_t<1, 1, false>(p, s);
+  return tab ? launch_sweep_t<1, 2, true>(p, s) : launch_sweep_t<1, 2, false>(p, s);
 }
 
 }  // namespace adr

@@ -227,6 +227,60 @@ def test_zero_pivot_and_nonfinite(adr):
     assert res.status == adr.OK and res.iters == 0 and not host(res.x).any()
 
 
+@pytest.mark.parametrize("scheme,bc,precision", [(0, 0, "fp64"), (1, 1, "fp64"), (1, 0, "fp32_factors"),
+                                               (0, 1, "fp32_sweeps")])
+def test_stencil_tables_change_no_bit(adr, scheme, bc, precision):
+    """An assembled operator is solved with S, W, E, N read from its column and
+    row tables; forbidding the tables (full diagonals) gives the same bits in
+    the preconditioner and in the whole solve."""
+    say("stencil tables", scheme, bc, precision)
+    prob = adr.assemble(0.05, 1.3, 0.8, 97, 75, scheme, bc)
+    assert prob.stencil_tables
+    prob.ilu0(precision)
+    q = np.random.default_rng(5).standard_normal(97 * 75)
+    z_tab = host(prob.precond(cuda(q)))
+    r_tab = prob.solve(1e-10, 3000)
+    x_tab = host(r_tab.x)
+    prob.use_stencil_tables(False)
+    assert not prob.stencil_tables
+    z_dia = host(prob.precond(cuda(q)))
+    r_dia = prob.solve(1e-10, 3000)
+    assert equal(z_tab, z_dia)
+    assert r_tab.status == r_dia.status and r_tab.iters == r_dia.iters
+    assert equal(x_tab, host(r_dia.x))
+    assert equal(r_tab.hist_l2, r_dia.hist_l2) and equal(r_tab.hist_max, r_dia.hist_max)
+    prob.use_stencil_tables(True)
+    assert prob.stencil_tables
+
+
+def test_operator_that_is_not_separable_uses_the_diagonals(adr):
+    """A matrix given through set_dia whose W varies along a column is
+    detected, solved from the full diagonals and matches the oracle; the
+    original (separable) matrix turns the tables back on."""
+    say("non-separable operator")
+    nx, ny = 64, 48
+    prob = adr.assemble(0.05, 1.0, 1.0, nx, ny, 1, 0)
+    orig = prob.get_dia()
+    d = {k: v.copy() for k, v in orig.items()}
+    d["W"][20 * nx + 30] *= 1.25
+    d["N"][7 * nx + 3] *= 0.75
+    prob.set_dia(**d)
+    assert not prob.stencil_tables
+    prob.ilu0()
+    f = prob.get_factors()
+    P = orc.Problem(0.05, 1.0, 1.0, nx, ny, 1, 0, d["S"], d["W"], d["C"], d["E"], d["N"], d["rhs"])
+    F = orc.ilu0(P)
+    assert equal(f["lw"], F.lw) and equal(f["invd"], F.invd)
+    q = np.random.default_rng(9).standard_normal(nx * ny)
+    assert equal(host(prob.precond(cuda(q))), orc.usolve(nx, ny, F, orc.lsolve(nx, ny, F, q)))
+    res = prob.solve(1e-10, 2000)
+    ref = orc.bicgstab(P, F, tol=1e-10, maxit=2000)
+    assert res.status == ref.status == orc.OK and abs(res.iters - ref.iters) <= 2
+    assert maxrel(host(res.x), ref.x) <= 1e-9
+    prob.set_dia(**orig)
+    assert prob.stencil_tables
+
+
 def test_argument_errors(adr):
     with pytest.raises(adr.AdrError):
         adr.assemble(0.0, 1.0, 1.0, 8, 8)
