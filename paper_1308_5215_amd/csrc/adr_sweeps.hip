@@ -238,8 +238,19 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   if (wave >= 3) {
     // ------------------------------------------------------------ loaders
     const TF *f1 = (const TF *)p.f1 + I.off, *f2 = (const TF *)p.f2 + I.off, *f3 = (const TF *)p.f3 + I.off;
-    const double *Wc = TAB ? p.tab + I.tab_off : nullptr;
-    const double *Ec = Wc + nx, *Sr = Wc + 2 * nx, *Nr = Sr + ny;
+    // stencil tables of the instance: Wc[nx], Ec[nx], Sr[ny], Nr[ny]
+    const double *tab = TAB ? p.tab + I.tab_off : nullptr;
+    // the row entry (S for L, N for U) of each strip row this lane loads is
+    // the same in every chunk: read once
+    double rowv[TAB ? NP : 1];
+    if (TAB) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int l = 1 + q * RPP + lr;
+        const int gj = (l <= rows) ? grow(l) : 0;
+        rowv[q] = tab[2 * nx + (OP == 0 ? 0 : ny) + gj];
+      }
+    }
     for (int c = wave - 3; c < nchunks; c += NLD) {
       // every load of the tile is issued before any is used (points outside
       // the strip load element 0 and are zeroed afterwards), so the loads
@@ -263,13 +274,13 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
           const double *invd = (const double *)f3;
           iw[q] = invd[gi > 0 ? k - 1 : k];
           is[q] = invd[gj > 0 ? k - nx : k];
-          bf[0][q] = (TF)Wc[gi];
-          bf[1][q] = (TF)Sr[gj];
+          bf[0][q] = (TF)tab[gi];           // W(i)
+          bf[1][q] = (TF)rowv[q];           // S(j)
           fi[q] = gi;
           fj[q] = gj;
         } else if (TAB) {
-          bf[0][q] = (TF)Ec[gi];
-          bf[1][q] = (TF)Nr[gj];
+          bf[0][q] = (TF)tab[nx + gi];      // E(i)
+          bf[1][q] = (TF)rowv[q];           // N(j)
           bf[NIN - 2][q] = f3[k];
         } else {
           bf[0][q] = f1[k];
