@@ -89,6 +89,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_us(prob, fns, reps):
+    """Mean device time (us) per call of each of `fns`, called in turn `reps`
+    times (L sweep then U sweep, as in the solve, so the U sweep reads the
+    vector the L sweep has just written): the library records HIP events on
+    the problem's stream around the launches of each single-step call (a
+    whole-loop event pair would also count the host's turnaround between
+    these synchronous calls)."""
+    for fn in fns.values():
+        fn()
+    total = dict.fromkeys(fns, 0.0)
+    for _ in range(reps):
+        for name, fn in fns.items():
+            fn()
+            total[name] += prob.last_call_ms
+    return {name: t * 1e3 / reps for name, t in total.items()}
+
+
 def sweep_source_hash():
     h = hashlib.sha256()
     for f in ("adr_sweeps.hip", "adr_kernels.hip"):
@@ -343,18 +360,9 @@ def run_large(args):
         prob = adr.assemble(eps, X, Y, n, n, "centered", "dirichlet")
         prob.ilu0(prec)
         kernels[prec] = {}
-        for name, fn in (("lsweep", lambda: prob.lsolve(q, out=y)), ("usweep", lambda: prob.usolve(y, out=z)),
-                         ("spmv", lambda: prob.spmv(q, out=z))):
-            fn()
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.kernel_reps):
-                fn()
-            e1.record(stream)
-            e1.synchronize()
-            us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
+        times = kernel_us(prob, {"lsweep": lambda: prob.lsolve(q, out=y), "usweep": lambda: prob.usolve(y, out=z),
+                                 "spmv": lambda: prob.spmv(q, out=z)}, args.kernel_reps)
+        for name, us in times.items():
             gbs = kb[name] * N / (us * 1e-6) / 1e9
             kernels[prec][name] = dict(avg_us=round(us, 1), bytes_per_unknown=kb[name], gbs=round(gbs, 1),
                                        frac=round(gbs / PEAK_HBM_GBS, 4))
@@ -485,18 +493,9 @@ def main():
     y = torch.empty_like(q)
     z = torch.empty_like(q)
     kern = {}
-    for name, fn in (("lsweep", lambda: prob.lsolve(q, out=y)), ("usweep", lambda: prob.usolve(y, out=z)),
-                     ("spmv", lambda: prob.spmv(q, out=z))):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.kernel_reps):
-            fn()
-        e1.record(stream)
-        e1.synchronize()
-        us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
+    times = kernel_us(prob, {"lsweep": lambda: prob.lsolve(q, out=y), "usweep": lambda: prob.usolve(y, out=z),
+                             "spmv": lambda: prob.spmv(q, out=z)}, args.kernel_reps)
+    for name, us in times.items():
         b = BYTES[name] * N
         kern[name] = dict(avg_us=us, algorithmic_bytes=b, gbs=b / (us * 1e-6) / 1e9)
         log("  %s: %.1f us  %.0f GB/s" % (name, us, kern[name]["gbs"]))

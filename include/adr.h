@@ -261,6 +261,13 @@ adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
 adr_status adr_use_stencil_tables(adr_problem *p, int32_t enable);
 int32_t adr_stencil_tables(const adr_problem *p);
 
+/* Device time in ms of the kernels of the last adr_spmv, adr_precond,
+ * adr_lsolve or adr_usolve call on p: HIP events recorded on the problem's
+ * stream right before the first and after the last launch of the call, so
+ * the host's turnaround between calls is not included.  0 before any such
+ * call or for p == NULL. */
+double adr_last_call_ms(const adr_problem *p);
+
 const char *adr_status_str(int32_t status);
 /* Message of the last call error on this thread ("" if none). */
 const char *adr_last_error(void);

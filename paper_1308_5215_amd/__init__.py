@@ -178,6 +178,12 @@ class Problem:
         return bool(_lib.load().adr_stencil_tables(self._h))
 
     @property
+    def last_call_ms(self):
+        """Device time (ms) of the kernels of the last spmv / precond /
+        lsolve / usolve call (HIP events on the problem's stream)."""
+        return float(_lib.load().adr_last_call_ms(self._h))
+
+    @property
     def device_bytes(self):
         return int(_lib.load().adr_device_bytes(self._h))
 

@@ -148,6 +148,9 @@ struct adr_problem {
   int *err = nullptr;
   // host pinned mirror of the states
   SolveState *h_st = nullptr;
+  // events bracketing the kernels of a single-step call (and the autotuner)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  float last_ms = 0.f;
   // captured iteration chunk
   hipGraphExec_t gexec = nullptr;
   double *g_x = nullptr;
@@ -211,6 +214,19 @@ adr_status ensure_sync(adr_problem *P) {
   HIP_TRY(launch_fill_u32(P->ticket, 2, 0u, P->stream));
   HIP_TRY(launch_fill_u64(P->handoff, words, HANDOFF_EMPTY, P->stream));
   HIP_TRY(hipMemsetAsync(P->err, 0, sizeof(int), P->stream));
+  return ADR_OK;
+}
+
+adr_status ensure_events(adr_problem *P) {
+  if (!P->ev0) HIP_TRY(hipEventCreate(&P->ev0));
+  if (!P->ev1) HIP_TRY(hipEventCreate(&P->ev1));
+  return ADR_OK;
+}
+
+// Device time between the two events of the problem (after they completed).
+adr_status read_call_ms(adr_problem *P) {
+  HIP_TRY(hipEventSynchronize(P->ev1));
+  HIP_TRY(hipEventElapsedTime(&P->last_ms, P->ev0, P->ev1));
   return ADR_OK;
 }
 
@@ -463,6 +479,8 @@ void adr_destroy(adr_problem *P) {
   dfree(P->d_feat);
   dfree(P->tab_bad);
   if (P->h_st) (void)hipHostFree(P->h_st);
+  if (P->ev0) (void)hipEventDestroy(P->ev0);
+  if (P->ev1) (void)hipEventDestroy(P->ev1);
   delete P;
 }
 
@@ -604,6 +622,8 @@ adr_status adr_use_stencil_tables(adr_problem *P, int32_t enable) {
 
 int32_t adr_stencil_tables(const adr_problem *P) { return (P && P->stencil_tab()) ? 1 : 0; }
 
+double adr_last_call_ms(const adr_problem *P) { return P ? (double)P->last_ms : 0.0; }
+
 adr_status adr_batch_ilu0(adr_problem *P, int32_t precision, int64_t *bad_index) {
   g_last_error.clear();
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
@@ -657,26 +677,41 @@ adr_status adr_spmv(adr_problem *P, const double *x, double *v) {
   if (st != ADR_OK) return st;
   if (!x || !v) return fail(ADR_ERR_ARG, "NULL argument");
   const Inst &I = P->inst[0];
+  st = ensure_events(P);
+  if (st != ADR_OK) return st;
+  HIP_TRY(hipEventRecord(P->ev0, P->stream));
   HIP_TRY(launch_spmv(P->dia(), I.fd, I.nx, I.ny, x, v, make_geom(I.n), P->stream));
+  HIP_TRY(hipEventRecord(P->ev1, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
-  return ADR_OK;
+  return read_call_ms(P);
 }
 
 adr_status adr_lsolve(adr_problem *P, const double *q, double *y) {
   g_last_error.clear();
   if (!P || !q || !y) return fail(ADR_ERR_ARG, "NULL argument");
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
-  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->stencil_tab(), q, y, P->sync(), nullptr, P->stream));
-  return check_device_fault(P);
+  adr_status st = ensure_events(P);
+  if (st != ADR_OK) return st;
+  HIP_TRY(hipEventRecord(P->ev0, P->stream));
+  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->stencil_tab(), q, y, P->sync(), nullptr,
+                        P->stream));
+  HIP_TRY(hipEventRecord(P->ev1, P->stream));
+  st = check_device_fault(P);
+  return st != ADR_OK ? st : read_call_ms(P);
 }
 
 adr_status adr_usolve(adr_problem *P, const double *y, double *z) {
   g_last_error.clear();
   if (!P || !y || !z) return fail(ADR_ERR_ARG, "NULL argument");
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
-  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->stencil_tab(), y, z, P->sync(), nullptr,
-                        P->stream));
-  return check_device_fault(P);
+  adr_status st = ensure_events(P);
+  if (st != ADR_OK) return st;
+  HIP_TRY(hipEventRecord(P->ev0, P->stream));
+  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->stencil_tab(), y, z, P->sync(),
+                        nullptr, P->stream));
+  HIP_TRY(hipEventRecord(P->ev1, P->stream));
+  st = check_device_fault(P);
+  return st != ADR_OK ? st : read_call_ms(P);
 }
 
 adr_status adr_precond(adr_problem *P, const double *q, double *z) {
@@ -684,11 +719,16 @@ adr_status adr_precond(adr_problem *P, const double *q, double *z) {
   if (!P || !q || !z) return fail(ADR_ERR_ARG, "NULL argument");
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
   adr_status st = ensure_iter_buffers(P, 0);
+  if (st == ADR_OK) st = ensure_events(P);
   if (st != ADR_OK) return st;
-  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->stencil_tab(), q, P->y, P->sync(), nullptr, P->stream));
-  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->stencil_tab(), P->y, z, P->sync(), nullptr,
+  HIP_TRY(hipEventRecord(P->ev0, P->stream));
+  HIP_TRY(launch_lsweep(P->geom(), P->precision, f64_of(P), f32_of(P), P->stencil_tab(), q, P->y, P->sync(), nullptr,
                         P->stream));
-  return check_device_fault(P);
+  HIP_TRY(launch_usweep(P->geom(), P->precision, P->dia(), f64_of(P), f32_of(P), P->stencil_tab(), P->y, z, P->sync(),
+                        nullptr, P->stream));
+  HIP_TRY(hipEventRecord(P->ev1, P->stream));
+  st = check_device_fault(P);
+  return st != ADR_OK ? st : read_call_ms(P);
 }
 
 adr_status adr_autotune(adr_problem *P, int32_t *rows_chosen, double *ms_per_apply) {
@@ -696,14 +736,13 @@ adr_status adr_autotune(adr_problem *P, int32_t *rows_chosen, double *ms_per_app
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
   if (!P->factored) return fail(ADR_ERR_STATE, "no factorisation (call adr_ilu0 first)");
   adr_status st = ensure_iter_buffers(P, 0);
+  if (st == ADR_OK) st = ensure_events(P);
   if (st != ADR_OK) return st;
   // time M^{-1} applied to the batch's right-hand sides for every strip height
   const int cand[] = {15, 31};
   int best = P->rows;
   float best_ms = -1.f;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  hipEvent_t e0 = P->ev0, e1 = P->ev1;
   for (int R : cand) {
     st = set_rows(P, R);
     if (st != ADR_OK) return st;
@@ -727,8 +766,6 @@ adr_status adr_autotune(adr_problem *P, int32_t *rows_chosen, double *ms_per_app
       best = R;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   st = set_rows(P, best);
   if (st != ADR_OK) return st;
   if (rows_chosen) *rows_chosen = best;
@@ -800,9 +837,9 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
     return true;
   };
   const size_t stb = sizeof(SolveState) * (size_t)P->count;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  st = ensure_events(P);
+  if (st != ADR_OK) return st;
+  hipEvent_t e0 = P->ev0, e1 = P->ev1;
   HIP_TRY(hipEventRecord(e0, P->stream));
   HIP_TRY(launch_init(B, g, P->stream));
   // replay chunks; keep one chunk queued behind the one being checked
@@ -838,8 +875,6 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
   HIP_TRY(hipStreamSynchronize(P->stream));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   st = check_device_fault(P);
   if (st != ADR_OK) return st;
   adr_status result = ADR_OK;

@@ -251,6 +251,9 @@ def test_stencil_tables_change_no_bit(adr, scheme, bc, precision):
     assert equal(r_tab.hist_l2, r_dia.hist_l2) and equal(r_tab.hist_max, r_dia.hist_max)
     prob.use_stencil_tables(True)
     assert prob.stencil_tables
+    # single-step calls report the device time of their kernels
+    prob.usolve(cuda(q))
+    assert 0.0 < prob.last_call_ms < 1000.0
 
 
 def test_operator_that_is_not_separable_uses_the_diagonals(adr):
