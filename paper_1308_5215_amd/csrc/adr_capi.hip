@@ -146,6 +146,7 @@ struct adr_problem {
   uint64_t *handoff = nullptr;
   int64_t handoff_words = 0;
   int *err = nullptr;
+  int sync_ready = 0;   // the three above allocated and initialised
   // host pinned mirror of the states
   SolveState *h_st = nullptr;
   // events bracketing the kernels of a single-step call (and the autotuner)
@@ -203,17 +204,21 @@ adr_status build_table(adr_problem *P, int R) {
   return ADR_OK;
 }
 
+// Allocation helpers below allocate each missing buffer on its own, so a call
+// that failed part-way (out of memory) leaves no null buffer behind a
+// non-null one for the next call to trust.
 adr_status ensure_sync(adr_problem *P) {
-  if (P->ticket) return ADR_OK;
+  if (P->sync_ready) return ADR_OK;
   int64_t words = 0;   // enough for the smallest strip height
   for (int k = 0; k < P->count; ++k) words += (int64_t)((P->ny[k] + 14) / 15) * P->nx[k];
   P->handoff_words = words;
-  HIP_TRY(dalloc(&P->ticket, 2, P->bytes));
-  HIP_TRY(dalloc(&P->handoff, (size_t)words, P->bytes));
-  HIP_TRY(dalloc(&P->err, 1, P->bytes));
+  if (!P->ticket) HIP_TRY(dalloc(&P->ticket, 2, P->bytes));
+  if (!P->handoff) HIP_TRY(dalloc(&P->handoff, (size_t)words, P->bytes));
+  if (!P->err) HIP_TRY(dalloc(&P->err, 1, P->bytes));
   HIP_TRY(launch_fill_u32(P->ticket, 2, 0u, P->stream));
   HIP_TRY(launch_fill_u64(P->handoff, words, HANDOFF_EMPTY, P->stream));
   HIP_TRY(hipMemsetAsync(P->err, 0, sizeof(int), P->stream));
+  P->sync_ready = 1;
   return ADR_OK;
 }
 
@@ -246,12 +251,12 @@ adr_status check_device_fault(adr_problem *P) {
 }
 
 adr_status ensure_iter_buffers(adr_problem *P, int maxit) {
-  if (!P->r) {
-    double **vecs[] = {&P->r, &P->rh, &P->p, &P->v, &P->s, &P->t, &P->ph, &P->z, &P->y};
-    for (double **q : vecs) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
-    HIP_TRY(dalloc(&P->st, (size_t)P->count, P->bytes));
+  double **vecs[] = {&P->r, &P->rh, &P->p, &P->v, &P->s, &P->t, &P->ph, &P->z, &P->y};
+  for (double **q : vecs)
+    if (!*q) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
+  if (!P->st) HIP_TRY(dalloc(&P->st, (size_t)P->count, P->bytes));
+  if (!P->h_st)
     HIP_TRY(hipHostMalloc((void **)&P->h_st, sizeof(SolveState) * (size_t)P->count, hipHostMallocDefault));
-  }
   if (P->hist_cap < maxit + 1) {
     dfree(P->hist);
     P->hist_cap = 0;
@@ -398,10 +403,8 @@ adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double a
 // operators; a matrix given through adr_set_dia may not be separable).
 adr_status refresh_stencil_tables(adr_problem *P) {
   P->has_tab = 0;
-  if (!P->tab) {
-    HIP_TRY(dalloc(&P->tab, (size_t)P->tab_len, P->bytes));
-    HIP_TRY(dalloc(&P->tab_bad, 1, P->bytes));
-  }
+  if (!P->tab) HIP_TRY(dalloc(&P->tab, (size_t)P->tab_len, P->bytes));
+  if (!P->tab_bad) HIP_TRY(dalloc(&P->tab_bad, 1, P->bytes));
   HIP_TRY(launch_fill_u32(P->tab_bad, 1, 0u, P->stream));
   HIP_TRY(launch_stencil_tables(P->dia(), P->geom(), P->tab, P->tab_bad, P->stream));
   unsigned bad = 0;
@@ -632,14 +635,13 @@ adr_status adr_batch_ilu0(adr_problem *P, int32_t precision, int64_t *bad_index)
   if (precision < ADR_FP64 || precision > ADR_FP32_SWEEPS) return fail(ADR_ERR_ARG, "unknown precision %d", precision);
   adr_status st = ensure_sync(P);
   if (st != ADR_OK) return st;
-  if (!P->lw) {
-    HIP_TRY(dalloc(&P->lw, (size_t)P->ntot, P->bytes));
-    HIP_TRY(dalloc(&P->ls, (size_t)P->ntot, P->bytes));
-    HIP_TRY(dalloc(&P->invd, (size_t)P->ntot, P->bytes));
-  }
-  if (precision != ADR_FP64 && !P->lw32) {
+  double **dv[] = {&P->lw, &P->ls, &P->invd};
+  for (double **q : dv)
+    if (!*q) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
+  if (precision != ADR_FP64) {
     float **fv[] = {&P->lw32, &P->ls32, &P->invd32, &P->E32, &P->N32};
-    for (float **q : fv) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
+    for (float **q : fv)
+      if (!*q) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
   }
   P->factored = 0;
   HIP_TRY(launch_fill_u64((uint64_t *)P->bad, P->count, ~0ull, P->stream));
