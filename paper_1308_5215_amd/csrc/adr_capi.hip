@@ -151,6 +151,7 @@ struct adr_problem {
   SolveState *h_st = nullptr;
   // events bracketing the kernels of a single-step call (and the autotuner)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev_chunk = nullptr;   // marks the state copy of a replayed chunk
   float last_ms = 0.f;
   // captured iteration chunk
   hipGraphExec_t gexec = nullptr;
@@ -225,6 +226,7 @@ adr_status ensure_sync(adr_problem *P) {
 adr_status ensure_events(adr_problem *P) {
   if (!P->ev0) HIP_TRY(hipEventCreate(&P->ev0));
   if (!P->ev1) HIP_TRY(hipEventCreate(&P->ev1));
+  if (!P->ev_chunk) HIP_TRY(hipEventCreateWithFlags(&P->ev_chunk, hipEventDisableTiming));
   return ADR_OK;
 }
 
@@ -484,6 +486,7 @@ void adr_destroy(adr_problem *P) {
   if (P->h_st) (void)hipHostFree(P->h_st);
   if (P->ev0) (void)hipEventDestroy(P->ev0);
   if (P->ev1) (void)hipEventDestroy(P->ev1);
+  if (P->ev_chunk) (void)hipEventDestroy(P->ev_chunk);
   delete P;
 }
 
@@ -854,15 +857,12 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
   }
   while (!done && launched > 0) {
     HIP_TRY(hipMemcpyAsync(P->h_st, P->st, stb, hipMemcpyDeviceToHost, P->stream));
-    hipEvent_t ev;
-    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(ev, P->stream));
+    HIP_TRY(hipEventRecord(P->ev_chunk, P->stream));
     if (launched < max_chunks) {
       HIP_TRY(hipGraphLaunch(P->gexec, P->stream));
       ++launched;
     }
-    HIP_TRY(hipEventSynchronize(ev));
-    (void)hipEventDestroy(ev);
+    HIP_TRY(hipEventSynchronize(P->ev_chunk));
     if (all_done()) {
       done = true;
     } else if (launched >= max_chunks) {
