@@ -268,6 +268,24 @@ int32_t adr_stencil_tables(const adr_problem *p);
  * call or for p == NULL. */
 double adr_last_call_ms(const adr_problem *p);
 
+/* Caller-provided workspace.  By default the library allocates its device
+ * memory itself.  A caller that owns the device memory (e.g. a PyTorch
+ * tensor) can instead hand it the buffers created after assembly: the
+ * wavefront hand-off memory, the ILU(0) factors, the nine iteration vectors
+ * and the per-instance solve states.
+ * adr_workspace_bytes: bytes these need for factors of `precision`
+ * (adr_precision); 0 for p == NULL or an unknown precision.
+ * adr_bind_workspace: dev_ptr (device memory on the problem's device, 256-byte
+ * aligned) of `bytes` >= adr_workspace_bytes(p, ADR_FP64) bytes; the buffers
+ * are carved out of it in a fixed order.  Call once, after assembly and before
+ * adr_ilu0 / adr_batch_ilu0 / any solve (else ADR_ERR_STATE); a precision
+ * needing more than the buffer holds later fails with ADR_ERR_NOMEM.  The
+ * caller keeps the memory alive and untouched until adr_destroy, which does
+ * not free it.  Histories, the stencil tables and the assembly arrays stay
+ * library-allocated. */
+size_t adr_workspace_bytes(const adr_problem *p, int32_t precision);
+adr_status adr_bind_workspace(adr_problem *p, void *dev_ptr, size_t bytes);
+
 const char *adr_status_str(int32_t status);
 /* Message of the last call error on this thread ("" if none). */
 const char *adr_last_error(void);

@@ -74,7 +74,25 @@ class SolveResult:
         return h[1:] / h[:-1]
 
 
-class Problem:
+class _Workspace:
+    """Caller-owned device memory for the buffers a problem creates after
+    assembly (adr_workspace_bytes / adr_bind_workspace)."""
+
+    def workspace_bytes(self, precision="fp64"):
+        return int(_lib.load().adr_workspace_bytes(self._h, _PREC[precision]))
+
+    def bind_workspace(self, buf):
+        """buf: a contiguous CUDA tensor of at least workspace_bytes() bytes
+        (torch's allocator aligns it); call before ilu0.  The problem keeps a
+        reference to it until it is destroyed."""
+        if not (buf.is_cuda and buf.is_contiguous()):
+            raise ValueError("the workspace must be a contiguous CUDA tensor")
+        nbytes = buf.numel() * buf.element_size()
+        _lib.check(_lib.load().adr_bind_workspace(self._h, ctypes.c_void_p(buf.data_ptr()), nbytes))
+        self._ws = buf
+
+
+class Problem(_Workspace):
     """One assembled five-point system on the current device."""
 
     def __init__(self, handle, eps, X, Y, nx, ny, scheme, bc, stream):
@@ -217,7 +235,7 @@ class BatchResult:
     overall: int           # adr_batch_solve's return value
 
 
-class Batch:
+class Batch(_Workspace):
     """Many independent instances advanced together (adr_batch_* calls)."""
 
     def __init__(self, handle, params, stream):

@@ -87,6 +87,20 @@ void dfree(T *&p) {
   p = nullptr;
 }
 
+// Buffers created after assembly (sync memory, factors, iteration vectors,
+// solve states) come from the caller's workspace when one is bound, each
+// rounded to 256 bytes; otherwise from hipMalloc.
+constexpr size_t WS_ALIGN = 256;
+size_t ws_round(size_t count, size_t elem) {
+  const size_t b = (count ? count : 1) * elem;
+  return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN;
+}
+
+template <class T>
+hipError_t palloc(adr_problem *P, T **p, size_t count);
+template <class T>
+void pfree(adr_problem *P, T *&p);
+
 // Strip height from the grid alone (used until the autotuner has run).
 int default_rows(int max_ny) { return max_ny >= 2048 ? 31 : 15; }
 
@@ -147,6 +161,10 @@ struct adr_problem {
   int64_t handoff_words = 0;
   int *err = nullptr;
   int sync_ready = 0;   // the three above allocated and initialised
+  // caller workspace (adr_bind_workspace): the buffers created after assembly
+  // are carved out of it instead of being allocated
+  char *ws = nullptr;
+  size_t ws_bytes = 0, ws_used = 0;
   // host pinned mirror of the states
   SolveState *h_st = nullptr;
   // events bracketing the kernels of a single-step call (and the autotuner)
@@ -166,6 +184,42 @@ struct adr_problem {
 };
 
 namespace {
+
+template <class T>
+hipError_t palloc(adr_problem *P, T **p, size_t count) {
+  if (!P->ws) return dalloc(p, count, P->bytes);
+  const size_t b = ws_round(count, sizeof(T));
+  *p = nullptr;
+  if (P->ws_used + b > P->ws_bytes) return hipErrorOutOfMemory;
+  *p = (T *)(P->ws + P->ws_used);
+  P->ws_used += b;
+  return hipSuccess;
+}
+template <class T>
+void pfree(adr_problem *P, T *&p) {
+  const char *c = (const char *)p;
+  if (p && !(P->ws && c >= P->ws && c < P->ws + P->ws_bytes)) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+// Hand-off words for the smallest strip height of every instance.
+int64_t handoff_words(const adr_problem *P) {
+  int64_t words = 0;
+  for (int k = 0; k < P->count; ++k) words += (int64_t)((P->ny[k] + 14) / 15) * P->nx[k];
+  return words;
+}
+
+// Workspace bytes: sync memory, factors of `precision`, iteration vectors and
+// solve states, in the order and rounding palloc uses.
+size_t workspace_bytes(const adr_problem *P, int precision) {
+  const size_t n = (size_t)P->ntot;
+  size_t b = ws_round(2, sizeof(unsigned)) + ws_round((size_t)handoff_words(P), sizeof(uint64_t)) +
+             ws_round(1, sizeof(int));
+  b += 3 * ws_round(n, sizeof(double));
+  if (precision != ADR_FP64) b += 5 * ws_round(n, sizeof(float));
+  b += 9 * ws_round(n, sizeof(double)) + ws_round((size_t)P->count, sizeof(SolveState));
+  return b;
+}
 
 // (Re)build the instance table for strip height R and upload it.
 adr_status build_table(adr_problem *P, int R) {
@@ -210,12 +264,11 @@ adr_status build_table(adr_problem *P, int R) {
 // non-null one for the next call to trust.
 adr_status ensure_sync(adr_problem *P) {
   if (P->sync_ready) return ADR_OK;
-  int64_t words = 0;   // enough for the smallest strip height
-  for (int k = 0; k < P->count; ++k) words += (int64_t)((P->ny[k] + 14) / 15) * P->nx[k];
+  const int64_t words = handoff_words(P);   // enough for the smallest strip height
   P->handoff_words = words;
-  if (!P->ticket) HIP_TRY(dalloc(&P->ticket, 2, P->bytes));
-  if (!P->handoff) HIP_TRY(dalloc(&P->handoff, (size_t)words, P->bytes));
-  if (!P->err) HIP_TRY(dalloc(&P->err, 1, P->bytes));
+  if (!P->ticket) HIP_TRY(palloc(P, &P->ticket, 2));
+  if (!P->handoff) HIP_TRY(palloc(P, &P->handoff, (size_t)words));
+  if (!P->err) HIP_TRY(palloc(P, &P->err, 1));
   HIP_TRY(launch_fill_u32(P->ticket, 2, 0u, P->stream));
   HIP_TRY(launch_fill_u64(P->handoff, words, HANDOFF_EMPTY, P->stream));
   HIP_TRY(hipMemsetAsync(P->err, 0, sizeof(int), P->stream));
@@ -255,8 +308,8 @@ adr_status check_device_fault(adr_problem *P) {
 adr_status ensure_iter_buffers(adr_problem *P, int maxit) {
   double **vecs[] = {&P->r, &P->rh, &P->p, &P->v, &P->s, &P->t, &P->ph, &P->z, &P->y};
   for (double **q : vecs)
-    if (!*q) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
-  if (!P->st) HIP_TRY(dalloc(&P->st, (size_t)P->count, P->bytes));
+    if (!*q) HIP_TRY(palloc(P, q, (size_t)P->ntot));
+  if (!P->st) HIP_TRY(palloc(P, &P->st, (size_t)P->count));
   if (!P->h_st)
     HIP_TRY(hipHostMalloc((void **)&P->h_st, sizeof(SolveState) * (size_t)P->count, hipHostMallocDefault));
   if (P->hist_cap < maxit + 1) {
@@ -471,15 +524,15 @@ void adr_destroy(adr_problem *P) {
   if (P->cap) (void)hipStreamDestroy(P->cap);
   double *dv[] = {P->S, P->W, P->C, P->E, P->N, P->rhs, P->F, P->lw, P->ls, P->invd, P->r, P->rh,
                   P->p, P->v, P->s, P->t, P->ph, P->z, P->y, P->hist, P->scal, P->tab};
-  for (double *q : dv) dfree(q);
+  for (double *q : dv) pfree(P, q);
   float *fv[] = {P->lw32, P->ls32, P->invd32, P->E32, P->N32};
-  for (float *q : fv) dfree(q);
+  for (float *q : fv) pfree(P, q);
   dfree(P->partials);
-  dfree(P->st);
+  pfree(P, P->st);
   dfree(P->bad);
-  dfree(P->ticket);
-  dfree(P->handoff);
-  dfree(P->err);
+  pfree(P, P->ticket);
+  pfree(P, P->handoff);
+  pfree(P, P->err);
   dfree(P->d_inst);
   dfree(P->d_feat);
   dfree(P->tab_bad);
@@ -630,6 +683,26 @@ int32_t adr_stencil_tables(const adr_problem *P) { return (P && P->stencil_tab()
 
 double adr_last_call_ms(const adr_problem *P) { return P ? (double)P->last_ms : 0.0; }
 
+size_t adr_workspace_bytes(const adr_problem *P, int32_t precision) {
+  if (!P || precision < ADR_FP64 || precision > ADR_FP32_SWEEPS) return 0;
+  return workspace_bytes(P, precision);
+}
+
+adr_status adr_bind_workspace(adr_problem *P, void *dev_ptr, size_t bytes) {
+  g_last_error.clear();
+  if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
+  if (!dev_ptr) return fail(ADR_ERR_ARG, "workspace is NULL");
+  if ((uintptr_t)dev_ptr % WS_ALIGN) return fail(ADR_ERR_ARG, "workspace must be %zu-byte aligned", WS_ALIGN);
+  const size_t need = workspace_bytes(P, ADR_FP64);
+  if (bytes < need) return fail(ADR_ERR_ARG, "workspace of %zu bytes is below the %zu the problem needs", bytes, need);
+  if (P->ws || P->ticket || P->handoff || P->err || P->lw || P->ls || P->invd || P->lw32 || P->r || P->st)
+    return fail(ADR_ERR_STATE, "bind the workspace once, before adr_ilu0 / adr_batch_ilu0 and any solve");
+  P->ws = (char *)dev_ptr;
+  P->ws_bytes = bytes;
+  P->ws_used = 0;
+  return ADR_OK;
+}
+
 adr_status adr_batch_ilu0(adr_problem *P, int32_t precision, int64_t *bad_index) {
   g_last_error.clear();
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
@@ -640,11 +713,11 @@ adr_status adr_batch_ilu0(adr_problem *P, int32_t precision, int64_t *bad_index)
   if (st != ADR_OK) return st;
   double **dv[] = {&P->lw, &P->ls, &P->invd};
   for (double **q : dv)
-    if (!*q) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
+    if (!*q) HIP_TRY(palloc(P, q, (size_t)P->ntot));
   if (precision != ADR_FP64) {
     float **fv[] = {&P->lw32, &P->ls32, &P->invd32, &P->E32, &P->N32};
     for (float **q : fv)
-      if (!*q) HIP_TRY(dalloc(q, (size_t)P->ntot, P->bytes));
+      if (!*q) HIP_TRY(palloc(P, q, (size_t)P->ntot));
   }
   P->factored = 0;
   HIP_TRY(launch_fill_u64((uint64_t *)P->bad, P->count, ~0ull, P->stream));

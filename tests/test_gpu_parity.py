@@ -284,6 +284,51 @@ def test_operator_that_is_not_separable_uses_the_diagonals(adr):
     assert prob.stencil_tables
 
 
+def test_caller_workspace_gives_the_same_solve(adr):
+    """Factors, iteration vectors and hand-off memory carved out of a torch
+    tensor: the same bits as with the library's own allocations, less
+    library-allocated memory, and the binding rules enforced."""
+    say("workspace")
+    ref = adr.assemble(0.05, 1.0, 1.0, 90, 70, 1, 0)
+    ref.ilu0()
+    r0 = ref.solve(1e-10, 2000)
+    prob = adr.assemble(0.05, 1.0, 1.0, 90, 70, 1, 0)
+    need = prob.workspace_bytes()
+    assert need >= 12 * 90 * 70 * 8 and prob.workspace_bytes("fp32_factors") > need
+    with pytest.raises(adr.AdrError):     # too small
+        prob.bind_workspace(torch.empty(need - 256, dtype=torch.uint8, device="cuda"))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    prob.bind_workspace(ws)
+    with pytest.raises(adr.AdrError):     # only once
+        prob.bind_workspace(ws)
+    before = prob.device_bytes
+    prob.ilu0()
+    r1 = prob.solve(1e-10, 2000)
+    assert r1.status == r0.status and r1.iters == r0.iters
+    assert equal(host(r1.x), host(r0.x)) and equal(r1.hist_l2, r0.hist_l2)
+    # the library allocated only the histories beyond the assembly
+    assert prob.device_bytes - before < ref.device_bytes - before
+    with pytest.raises(adr.AdrError):     # FP32 factors need more than this workspace holds
+        prob.ilu0("fp32_factors")
+    # bound after ilu0: refused
+    late = adr.assemble(0.05, 1.0, 1.0, 20, 20, 0, 0)
+    late.ilu0()
+    with pytest.raises(adr.AdrError):
+        late.bind_workspace(torch.empty(late.workspace_bytes(), dtype=torch.uint8, device="cuda"))
+    # a batch
+    b = adr.assemble_batch([0.1, 0.3], [1.0, 1.5], [1.0, 0.7], [40, 33], [25, 50], ["upwind", "centered"],
+                           ["dirichlet", "neumann"])
+    wsb = torch.empty(b.workspace_bytes("fp32_factors"), dtype=torch.uint8, device="cuda")
+    b.bind_workspace(wsb)
+    b.ilu0("fp32_factors")
+    rb = b.solve(tol=1e-10, maxit=500)
+    b2 = adr.assemble_batch([0.1, 0.3], [1.0, 1.5], [1.0, 0.7], [40, 33], [25, 50], ["upwind", "centered"],
+                            ["dirichlet", "neumann"])
+    b2.ilu0("fp32_factors")
+    rb2 = b2.solve(tol=1e-10, maxit=500)
+    assert np.array_equal(rb.iters, rb2.iters) and equal(host(rb.x), host(rb2.x))
+
+
 def test_argument_errors(adr):
     with pytest.raises(adr.AdrError):
         adr.assemble(0.0, 1.0, 1.0, 8, 8)
