@@ -221,6 +221,25 @@ def assemble(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet", field=None, amp
     return Problem(h, float(eps), float(X), float(Y), int(nx), int(ny), sch, b, stream)
 
 
+def solve(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet", tol=1e-10, maxit=1000, precision="fp64",
+          x0=None, field=None, amp=0.0, stream=None):
+    """The method in one call: assemble (Section 4), ILU(0) (Section 5.1) and
+    BiCGSTAB (Section 5.2) to ||r|| < tol ||b||.  Returns
+    (x, hist_l2, hist_max, iters, status): x a CUDA float64 tensor, the
+    residual histories as numpy arrays, the pass count and the adr_status."""
+    prob = assemble(eps, X, Y, nx, ny, scheme, bc, field=field, amp=amp, stream=stream)
+    prob.ilu0(precision)
+    r = prob.solve(tol=tol, maxit=maxit, x0=x0)
+    return r.x, r.hist_l2, r.hist_max, r.iters, r.status
+
+
+def amplification(hist):
+    """||r^{k+1}|| / ||r^k|| of a residual history (the paper's amplification
+    factor, Section 6.5)."""
+    h = np.asarray(hist, dtype=np.float64)
+    return h[1:] / h[:-1]
+
+
 @dataclass
 class BatchResult:
     x: object              # batched CUDA float64 tensor

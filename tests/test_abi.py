@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -63,3 +64,9 @@ def test_status_numbering_matches_the_oracle():
     from paper_1308_5215_amd import _lib
     for name in ("OK", "ERR_ARG", "MAXIT", "BREAKDOWN_RHO", "OMEGA_ZERO", "ZERO_PIVOT", "NONFINITE"):
         assert getattr(core, name) == getattr(_lib, name)
+
+
+def test_amplification_helper():
+    """The paper's amplification factor ||r^{k+1}|| / ||r^k|| of a history."""
+    import paper_1308_5215_amd as adr
+    np.testing.assert_array_equal(adr.amplification([4.0, 2.0, 1.0, 0.25]), [0.5, 0.5, 0.25])

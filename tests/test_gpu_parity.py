@@ -329,6 +329,20 @@ def test_caller_workspace_gives_the_same_solve(adr):
     assert np.array_equal(rb.iters, rb2.iters) and equal(host(rb.x), host(rb2.x))
 
 
+def test_one_call_solve(adr):
+    """adr.solve: assemble, ilu0 and solve in one call, returning
+    (x, hist_l2, hist_max, iters, status) -- the oracle's result."""
+    say("one-call solve")
+    x, h2, hm, iters, status = adr.solve(0.1, 1.0, 1.0, 64, 64, "centered", "dirichlet", tol=1e-10, maxit=500)
+    P = oracle_problem(0.1, 1.0, 1.0, 64, 64, 1, 0)
+    ref = orc.bicgstab(P, orc.ilu0(P), tol=1e-10, maxit=500)
+    assert status == adr.OK == ref.status and abs(iters - ref.iters) <= 2
+    assert maxrel(host(x), ref.x) <= 1e-9
+    assert len(h2) == len(hm) == iters + 1
+    amp = adr.amplification(h2)
+    assert amp.shape == (iters,) and np.all(amp > 0)
+
+
 def test_argument_errors(adr):
     with pytest.raises(adr.AdrError):
         adr.assemble(0.0, 1.0, 1.0, 8, 8)
