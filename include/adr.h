@@ -242,7 +242,8 @@ adr_status adr_dot(const double *x_dev, const double *y_dev, int64_t n, void *st
 size_t adr_device_bytes(const adr_problem *p);
 
 /* Sweep geometry: rows per strip (R = 15 or 31) for the wavefront kernels,
- * or 0 to pick automatically.  For tuning and tests. */
+ * or 0 for the default (31, also the height a new problem starts with).
+ * Results do not depend on it.  For tuning and tests. */
 adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
 
 /* Stencil tables.  The off-diagonals of the operator of Section 4 are
