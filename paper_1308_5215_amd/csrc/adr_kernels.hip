@@ -1,6 +1,7 @@
-// HIP kernels for gfx950: assembly, five-point SpMV, double-double inner
-// products, and the BiCGSTAB vector updates with their single-block finalize
-// steps (the wavefront kernels are in adr_sweeps.hip).
+// HIP kernels for gfx950: assembly, the stencil tables (copy and bitwise
+// check), five-point SpMV, double-double inner products, and the BiCGSTAB
+// vector updates with their single-block finalize steps (the wavefront
+// kernels are in adr_sweeps.hip).
 //
 // Floating point: compiled with -ffp-contract=off; every fused multiply-add
 // is an explicit fma().  Every per-point formula below is the fixed
