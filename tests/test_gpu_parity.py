@@ -494,7 +494,8 @@ def test_mixed_precision_solve(adr, precision, scheme):
 BATCH = [  # eps, X, Y, nx, ny, scheme, bc
     (0.1, 1.0, 1.0, 64, 64, 0, 0), (2.0, 1.0, 1.0, 37, 53, 1, 1), (0.01, 1.0, 1.0, 130, 67, 1, 0),
     (0.5, 1.0, 1.0, 1, 40, 1, 0), (0.5, 1.0, 1.0, 45, 1, 0, 0), (0.01, 1.0, 1.0, 96, 96, 0, 1),
-    (0.003, 0.7, 1.6, 160, 128, 0, 0), (0.2, 1.9, 0.6, 33, 200, 1, 1)]
+    (0.003, 0.7, 1.6, 160, 128, 0, 0), (0.2, 1.9, 0.6, 33, 200, 1, 1), (0.3, 1.2, 0.8, 1, 1, 0, 1),
+    (0.05, 1.0, 1.0, 2, 3, 1, 0)]
 
 
 @pytest.mark.parametrize("with_field", [False, True])
