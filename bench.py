@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--rows", type=int, default=0, help="sweep strip height (0 = automatic)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--neumann-window", type=int, default=200)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", choices=("single", "batch", "warmstart", "kernels", "large"), default="single")
@@ -129,6 +129,20 @@ def traffic_for(kernel, workload):
         return float(e["bytes_per_launch"])
     except Exception:
         return None
+
+
+def _oracle_pass_seconds(job):
+    """Worker (own process): seconds per BiCGSTAB pass of the CPU oracle on one
+    instance of the batch, over a fixed window of passes (tol 0)."""
+    eps, X, Y, n, scheme, bc, field, passes, precision = job
+    from oracle import core as orc
+    P = orc.assemble(eps, X, Y, n, n, scheme, bc, field=field, amp=0.1)
+    F = orc.ilu0(P)
+    if precision == "fp32_factors":
+        F = orc.round_factors_f32(F)
+    t = time.perf_counter()
+    r = orc.bicgstab(P, F, tol=0.0, maxit=passes)
+    return (time.perf_counter() - t) / max(r.iters, 1), n * n
 
 
 def run_batch(args):
@@ -201,6 +215,31 @@ def run_batch(args):
         del prob, r1
     scale = len(inst) / len(sample)
     seq_s = seq_ms * scale / 1e3
+
+    # the CPU oracle, one instance per core: seconds per unknown-pass from a
+    # fixed window of passes on a sample of the instances, applied to the
+    # batch's own unknown-passes
+    cpu = None
+    if args.cpu_baseline:
+        import multiprocessing as mp
+        cores = max(1, min(16, os.cpu_count() or 1))
+        pick = np.linspace(0, len(inst) - 1, 16).round().astype(int)
+        jobs = [(inst[k]["eps"], inst[k]["X"], inst[k]["Y"], inst[k]["n"], inst[k]["scheme"], inst[k]["bc"],
+                 flds[k], 10, args.batch_precision) for k in pick]
+        log("cpu baseline (oracle): %d instances x 10 passes on %d processes" % (len(jobs), cores))
+        with mp.get_context("spawn").Pool(cores) as pool:
+            got = pool.map(_oracle_pass_seconds, jobs)
+        rate = sum(t for t, _ in got) / sum(m for _, m in got)     # s per unknown-pass, one core
+        single = rate * work
+        cpu = dict(value=round(single / cores, 2), unit="s", cores=cores, kind="oracle",
+                   single_core_s=round(single, 1),
+                   sample="10 BiCGSTAB passes of the FP64 oracle (%s factors) on each of %d instances spread "
+                          "over the batch, one process per core: %.1f ns per unknown-pass on one core, applied to "
+                          "the batch's %.3g unknown-passes and divided over %d cores (load balance assumed)"
+                          % ("FP32-rounded" if args.batch_precision == "fp32_factors" else "FP64",
+                             len(jobs), rate * 1e9, work, cores))
+        log("  %.1f ns per unknown-pass -> %.0f s on one core, %.0f s on %d" % (rate * 1e9, single, single / cores,
+                                                                              cores))
     out = {
         "metric": "time to rel-resid 1e-10, batched instances (FP32 preconditioner, FP64 Krylov)",
         "value": round(batch_s, 4), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -218,6 +257,7 @@ def run_batch(args):
                        "speedup_batched": round(seq_s / batch_s, 2) if batch_s > 0 else None,
                        "max_rel_diff_vs_batched": maxdiff},
         "sweep_rows": rows,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -539,7 +579,7 @@ def main():
 
     # ---- CPU baseline: the oracle on a bounded sample ----
     cpu = None
-    if not args.no_cpu_baseline:
+    if args.cpu_baseline:
         log("cpu baseline (oracle), ~%.0f s" % args.cpu_seconds)
         from oracle import core as orc
         P = orc.assemble(args.eps, 1.0, 1.0, n, n, orc.CENTERED, orc.DIRICHLET)
