@@ -108,7 +108,7 @@ def kernel_us(prob, fns, reps):
 
 def sweep_source_hash():
     h = hashlib.sha256()
-    for f in ("adr_sweeps.hip", "adr_kernels.hip"):
+    for f in ("adr_sweeps.hip", "adr_kernels.hip", "adr_device.h", "adr_internal.h"):
         with open(os.path.join(ROOT, "paper_1308_5215_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -153,13 +153,25 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
   return (t + n) >> f.s;
 }
 
+// Neighbour values of point k (0 outside the grid).  Every load is issued
+// unconditionally (an out-of-range neighbour reads x[k] and is then replaced
+// by 0), so the five loads of a point, and of the points a thread handles
+// together, are in flight at once instead of behind branches.
+struct Nbr {
+  double c, s, w, e, n;
+};
+__device__ __forceinline__ Nbr load_nbr(const double *__restrict__ x, int k, int i, int j, int nx, int ny) {
+  const bool hs = j > 0, hw = i > 0, he = i < nx - 1, hn = j < ny - 1;
+  const double vs = x[hs ? k - nx : k], vw = x[hw ? k - 1 : k], ve = x[he ? k + 1 : k];
+  const double vn = x[hn ? k + nx : k], vc = x[k];
+  return Nbr{vc, hs ? vs : 0.0, hw ? vw : 0.0, he ? ve : 0.0, hn ? vn : 0.0};
+}
+
 __device__ __forceinline__ double spmv_point(const Dia &A, const double *__restrict__ x, int k, int i,
                                              int j, int nx, int ny) {
-  const double xs = (j > 0) ? x[k - nx] : 0.0;
-  const double xw = (i > 0) ? x[k - 1] : 0.0;
-  const double xe = (i < nx - 1) ? x[k + 1] : 0.0;
-  const double xn = (j < ny - 1) ? x[k + nx] : 0.0;
-  double t = A.C[k] * x[k];
+  const Nbr v = load_nbr(x, k, i, j, nx, ny);
+  const double xs = v.s, xw = v.w, xe = v.e, xn = v.n;
+  double t = A.C[k] * v.c;
   t = fma(A.S[k], xs, t);
   t = fma(A.W[k], xw, t);
   t = fma(A.E[k], xe, t);
@@ -173,11 +185,9 @@ __device__ __forceinline__ double spmv_point_tab(const double *__restrict__ C, c
                                                  const double *__restrict__ x, int k, int i, int j, int nx,
                                                  int ny) {
   const double *Wc = tab, *Ec = tab + nx, *Sr = tab + 2 * nx, *Nr = Sr + ny;
-  const double xs = (j > 0) ? x[k - nx] : 0.0;
-  const double xw = (i > 0) ? x[k - 1] : 0.0;
-  const double xe = (i < nx - 1) ? x[k + 1] : 0.0;
-  const double xn = (j < ny - 1) ? x[k + nx] : 0.0;
-  double t = C[k] * x[k];
+  const Nbr v = load_nbr(x, k, i, j, nx, ny);
+  const double xs = v.s, xw = v.w, xe = v.e, xn = v.n;
+  double t = C[k] * v.c;
   t = fma(Sr[j], xs, t);
   t = fma(Wc[i], xw, t);
   t = fma(Ec[i], xe, t);

@@ -198,6 +198,13 @@ hipError_t launch_dot(const double *x, const double *y, const Stream1D &g, doubl
   const int end = min(beg + I.chunk, I.n);                                   \
   const int64_t o = I.off
 
+// The per-pass streaming kernels take UNR points per thread per loop trip
+// (k0, k0 + BLK, ...): all their loads are issued before any result is
+// stored, and the sums still run over the points in the order k0, k0 + BLK,
+// ...  Slots past the end load the last point again and are then dropped.
+constexpr int UNR = 4;
+__device__ __forceinline__ int unr_at(int k0, int u, int end) { return min(k0 + u * BLK, end - 1); }
+
 __device__ __forceinline__ double *hist_l2_of(const IterBufs &B, int i) {
   return B.hist + (size_t)i * 2 * (size_t)(B.maxit + 1);
 }
@@ -321,13 +328,32 @@ __global__ __launch_bounds__(BLK) void k_pass_p(IterBufs B, BatchGeom g) {
   ADR_BATCH_BLOCK(g);
   const SolveState &S = B.st[ii];
   if (S.phase != RUNNING) return;
-  double *p = B.p + o;
-  const double *r = B.r + o, *v = B.v + o;
+  double *__restrict__ p = B.p + o;
+  const double *__restrict__ r = B.r + o, *__restrict__ v = B.v + o;
   if (S.iter == 1) {
-    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) p[k] = r[k];
+    for (int k0 = beg + (int)threadIdx.x; k0 < end; k0 += UNR * BLK) {
+      double rk[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) rk[u] = r[unr_at(k0, u, end)];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        if (k0 + u * BLK < end) p[k0 + u * BLK] = rk[u];
+    }
   } else {
     const double beta = S.beta, omega = S.omega;
-    for (int k = beg + (int)threadIdx.x; k < end; k += BLK) p[k] = fma(beta, fma(-omega, v[k], p[k]), r[k]);
+    for (int k0 = beg + (int)threadIdx.x; k0 < end; k0 += UNR * BLK) {
+      double pk[UNR], rk[UNR], vk[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int k = unr_at(k0, u, end);
+        pk[u] = p[k];
+        rk[u] = r[k];
+        vk[u] = v[k];
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        if (k0 + u * BLK < end) p[k0 + u * BLK] = fma(beta, fma(-omega, vk[u], pk[u]), rk[u]);
+    }
   }
 }
 hipError_t launch_pass_p(const IterBufs &B, const BatchGeom &g, hipStream_t s) {
@@ -350,14 +376,25 @@ __global__ __launch_bounds__(BLK) void k_pass_v(IterBufs B, BatchGeom g) {
   if (B.st[ii].phase != RUNNING) return;
   Dia A{B.A.S + o, B.A.W + o, B.A.C + o, B.A.E + o, B.A.N + o};
   const double *tab = TAB ? B.tab + I.tab_off : nullptr;
-  const double *ph = B.ph + o, *rh = B.rh + o;
-  double *v = B.v + o;
+  const double *__restrict__ ph = B.ph + o, *__restrict__ rh = B.rh + o;
+  double *__restrict__ v = B.v + o;
   dd acc[1] = {dd{0.0, 0.0}};
-  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
-    const double vk = stencil_point<TAB>(A, tab, ph, k, i, j, I.nx, I.ny);
-    v[k] = vk;
-    acc[0] = dd_add(acc[0], dd_prod(rh[k], vk));
+  for (int k0 = beg + (int)threadIdx.x; k0 < end; k0 += UNR * BLK) {
+    double vk[UNR], rk[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int k = unr_at(k0, u, end);
+      const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
+      vk[u] = stencil_point<TAB>(A, tab, ph, k, i, j, I.nx, I.ny);
+      rk[u] = rh[k];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      if (k0 + u * BLK < end) {
+        v[k0 + u * BLK] = vk[u];
+        acc[0] = dd_add(acc[0], dd_prod(rk[u], vk[u]));
+      }
+    }
   }
   block_partials<1, false>(acc, 0.0, B.partials, g.nblk, blockIdx.x);
 }
@@ -383,15 +420,27 @@ __global__ __launch_bounds__(BLK) void k_pass_s(IterBufs B, BatchGeom g) {
   ADR_BATCH_BLOCK(g);
   if (B.st[ii].phase != RUNNING) return;
   const double alpha = B.st[ii].alpha;
-  const double *r = B.r + o, *v = B.v + o;
-  double *sv = B.s + o;
+  const double *__restrict__ r = B.r + o, *__restrict__ v = B.v + o;
+  double *__restrict__ sv = B.s + o;
   dd acc[1] = {dd{0.0, 0.0}};
   double mx = 0.0;
-  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    const double sk = fma(-alpha, v[k], r[k]);
-    sv[k] = sk;
-    acc[0] = dd_add(acc[0], dd_prod(sk, sk));
-    mx = nanmax(mx, fabs(sk));
+  for (int k0 = beg + (int)threadIdx.x; k0 < end; k0 += UNR * BLK) {
+    double rk[UNR], vk[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int k = unr_at(k0, u, end);
+      rk[u] = r[k];
+      vk[u] = v[k];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      if (k0 + u * BLK < end) {
+        const double sk = fma(-alpha, vk[u], rk[u]);
+        sv[k0 + u * BLK] = sk;
+        acc[0] = dd_add(acc[0], dd_prod(sk, sk));
+        mx = nanmax(mx, fabs(sk));
+      }
+    }
   }
   block_partials<1, true>(acc, mx, B.partials, g.nblk, blockIdx.x);
 }
@@ -427,15 +476,26 @@ __global__ __launch_bounds__(BLK) void k_pass_t(IterBufs B, BatchGeom g) {
   if (B.st[ii].phase != RUNNING) return;
   Dia A{B.A.S + o, B.A.W + o, B.A.C + o, B.A.E + o, B.A.N + o};
   const double *tab = TAB ? B.tab + I.tab_off : nullptr;
-  const double *z = B.z + o, *sv = B.s + o;
-  double *t = B.t + o;
+  const double *__restrict__ z = B.z + o, *__restrict__ sv = B.s + o;
+  double *__restrict__ t = B.t + o;
   dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
-  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
-    const double tk = stencil_point<TAB>(A, tab, z, k, i, j, I.nx, I.ny);
-    t[k] = tk;
-    acc[0] = dd_add(acc[0], dd_prod(tk, sv[k]));
-    acc[1] = dd_add(acc[1], dd_prod(tk, tk));
+  for (int k0 = beg + (int)threadIdx.x; k0 < end; k0 += UNR * BLK) {
+    double tk[UNR], sk[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int k = unr_at(k0, u, end);
+      const int j = (int)fdiv((uint32_t)k, I.fd), i = k - j * I.nx;
+      tk[u] = stencil_point<TAB>(A, tab, z, k, i, j, I.nx, I.ny);
+      sk[u] = sv[k];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      if (k0 + u * BLK < end) {
+        t[k0 + u * BLK] = tk[u];
+        acc[0] = dd_add(acc[0], dd_prod(tk[u], sk[u]));
+        acc[1] = dd_add(acc[1], dd_prod(tk[u], tk[u]));
+      }
+    }
   }
   block_partials<2, false>(acc, 0.0, B.partials, g.nblk, blockIdx.x);
 }
@@ -465,24 +525,42 @@ __global__ __launch_bounds__(BLK) void k_pass_xr(IterBufs B, BatchGeom g) {
   const int phase = B.st[ii].phase;
   if (phase == DONE) return;
   const double alpha = B.st[ii].alpha;
-  double *x = B.x + o;
-  const double *ph = B.ph + o;
+  double *__restrict__ x = B.x + o;
+  const double *__restrict__ ph = B.ph + o;
   if (phase == HALF_STEP) {
     for (int k = beg + (int)threadIdx.x; k < end; k += BLK) x[k] = fma(alpha, ph[k], x[k]);
     return;
   }
   const double omega = B.st[ii].omega;
-  const double *z = B.z + o, *t = B.t + o, *sv = B.s + o, *rh = B.rh + o;
-  double *r = B.r + o;
+  const double *__restrict__ z = B.z + o, *__restrict__ t = B.t + o, *__restrict__ sv = B.s + o;
+  const double *__restrict__ rh = B.rh + o;
+  double *__restrict__ r = B.r + o;
   dd acc[2] = {dd{0.0, 0.0}, dd{0.0, 0.0}};
   double mx = 0.0;
-  for (int k = beg + (int)threadIdx.x; k < end; k += BLK) {
-    x[k] = fma(omega, z[k], fma(alpha, ph[k], x[k]));
-    const double rk = fma(-omega, t[k], sv[k]);
-    r[k] = rk;
-    acc[0] = dd_add(acc[0], dd_prod(rk, rk));
-    acc[1] = dd_add(acc[1], dd_prod(rh[k], rk));
-    mx = nanmax(mx, fabs(rk));
+  for (int k0 = beg + (int)threadIdx.x; k0 < end; k0 += UNR * BLK) {
+    double xk[UNR], pk[UNR], zk[UNR], tk[UNR], sk[UNR], hk[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int k = unr_at(k0, u, end);
+      xk[u] = x[k];
+      pk[u] = ph[k];
+      zk[u] = z[k];
+      tk[u] = t[k];
+      sk[u] = sv[k];
+      hk[u] = rh[k];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int k = k0 + u * BLK;
+      if (k < end) {
+        x[k] = fma(omega, zk[u], fma(alpha, pk[u], xk[u]));
+        const double rk = fma(-omega, tk[u], sk[u]);
+        r[k] = rk;
+        acc[0] = dd_add(acc[0], dd_prod(rk, rk));
+        acc[1] = dd_add(acc[1], dd_prod(hk[u], rk));
+        mx = nanmax(mx, fabs(rk));
+      }
+    }
   }
   block_partials<2, true>(acc, mx, B.partials, g.nblk, blockIdx.x);
 }
