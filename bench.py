@@ -131,6 +131,18 @@ def traffic_for(kernel, workload):
         return None
 
 
+def host_cpu():
+    """Model name of the host CPU that runs the oracle (Linux), else ""."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def _oracle_pass_seconds(job):
     """Worker (own process): seconds per BiCGSTAB pass of the CPU oracle on one
     instance of the batch, over a fixed window of passes (tol 0)."""
@@ -232,7 +244,7 @@ def run_batch(args):
         rate = sum(t for t, _ in got) / sum(m for _, m in got)     # s per unknown-pass, one core
         single = rate * work
         cpu = dict(value=round(single / cores, 2), unit="s", cores=cores, kind="oracle",
-                   single_core_s=round(single, 1),
+                   single_core_s=round(single, 1), host=host_cpu(),
                    sample="10 BiCGSTAB passes of the FP64 oracle (%s factors) on each of %d instances spread "
                           "over the batch, one process per core: %.1f ns per unknown-pass on one core, applied to "
                           "the batch's %.3g unknown-passes and divided over %d cores (load balance assumed)"
@@ -595,7 +607,7 @@ def main():
                 break
             k = max(k + 1, int(args.cpu_seconds / 2 / max(t_pass, 1e-9)))
         est = t_pass * mean_iters
-        cpu = dict(value=round(est, 2), unit="s", cores=1, kind="oracle",
+        cpu = dict(value=round(est, 2), unit="s", cores=1, kind="oracle", host=host_cpu(),
                    sample="%d BiCGSTAB passes of the single-threaded FP64 oracle on the %dx%d centered grid "
                           "(%.3f s per pass), extrapolated to the GPU's mean pass count %.0f" %
                           (k, n, n, t_pass, mean_iters, ))
