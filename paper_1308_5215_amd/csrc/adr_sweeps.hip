@@ -188,11 +188,15 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   using TF = typename std::conditional<PREC == 0, double, float>::type;
   using CT = typename std::conditional<PREC == 2, float, double>::type;
   constexpr int NIN = (OP == 0) ? 3 : 4;
-  using Sh = SweepShape<R, NIN, (int)sizeof(CT)>;
+  // The table-driven U sweep keeps N, which is the same along a strip row, in
+  // a register of that row's lane: its ring tiles hold y, E and invd only.
+  constexpr bool NREG = (OP == 1) && TAB;
+  constexpr int NL = NREG ? 3 : NIN;   // arrays per ring tile (U: invd last)
+  using Sh = SweepShape<R, NL, (int)sizeof(CT)>;
   constexpr int W = Sh::W, L = Sh::L, PITCH = Sh::PITCH, NC = Sh::NC, NT = Sh::NT, NLD = Sh::NLD;
   constexpr int RPP = Sh::RPP, NP = Sh::NP;
   static_assert(L <= 64, "strip too tall");
-  __shared__ __align__(16) CT s_in[NC][NIN][L][PITCH];
+  __shared__ __align__(16) CT s_in[NC][NL][L][PITCH];
   __shared__ __align__(16) double s_out[2][L][PITCH];
   __shared__ __align__(8) int s_flag[NC][2];   // [slot]{loaded, ghost}: chunk index + 1
   __shared__ int s_computed, s_stored;
@@ -212,9 +216,9 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
     s_flag[tid][1] = 0;
   }
   // ghost row of every ring slot: zero values and coefficients (invd = 1)
-  for (int e = tid; e < NC * NIN * PITCH; e += NT) {
-    const int sl = e / (NIN * PITCH), m = (e / PITCH) % NIN, w = e % PITCH;
-    s_in[sl][m][0][w] = (OP == 1 && m == 3) ? (CT)1 : (CT)0;
+  for (int e = tid; e < NC * NL * PITCH; e += NT) {
+    const int sl = e / (NL * PITCH), m = (e / PITCH) % NL, w = e % PITCH;
+    s_in[sl][m][0][w] = (OP == 1 && m == NL - 1) ? (CT)1 : (CT)0;
   }
   __syncthreads();
   const int strip = s_strip;
@@ -303,7 +307,10 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
         if (l < L) {
           s_in[sl][0][l][lc] = okq[q] ? (CT)bv[q] : (CT)0;
 #pragma unroll
-          for (int m = 1; m < NIN; ++m) s_in[sl][m][l][lc] = okq[q] ? (CT)bf[m - 1][q] : (CT)0;
+          for (int m = 1; m < NIN; ++m) {
+            if (NREG && m == 2) continue;   // N: the compute wave's register
+            s_in[sl][(NREG && m == 3) ? 2 : m][l][lc] = okq[q] ? (CT)bf[m - 1][q] : (CT)0;
+          }
         }
       }
       lds_put(&s_flag[sl][0], c + 1);
@@ -388,6 +395,14 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
     // ------------------------------------------------------------- compute
     uint64_t *ho_out = const_cast<uint64_t *>(ho_base) + (size_t)strip * nx;
     const int row = lane < L ? lane : L - 1;
+    // NREG: N of this lane's strip row (0 for the ghost lane and rows past the
+    // strip).  Unlike the tiles it is not zeroed at the (never stored) points
+    // left or right of the grid; there y, E and invd are 0 and the value from
+    // the row below is itself such a point's +-0, so they still come out +-0
+    // (NaN only if the neighbour in x already is), as with a zero N.
+    CT nrow = (CT)0;
+    if (NREG && lane >= 1 && lane < L && lane <= rows)
+      nrow = (CT)(TF)p.tab[I.tab_off + 2 * nx + ny + grow(lane)];
     CT west = (CT)0;
     uint64_t fl = lds_peek_pair(&s_flag[0][0]);
     for (int c = 0; c < nchunks; ++c) {
@@ -404,19 +419,19 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
       int st = lds_peek(&s_stored);
       // the whole chunk's inputs into registers first, so that LDS latency is
       // paid once per chunk and not inside the dependent chain
-      CT in[NIN][W];
+      CT in[NL][W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
 #pragma unroll
-        for (int m = 0; m < NIN; ++m) in[m][w] = s_in[sl][m][row][w];
+        for (int m = 0; m < NL; ++m) in[m][w] = s_in[sl][m][row][w];
       }
       __builtin_amdgcn_sched_barrier(0);
       CT res[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         const CT south = dpp_up(west);
-        CT v = fma(-in[2][w], south, fma(-in[1][w], west, in[0][w]));
-        if (OP == 1) v = v * in[NIN - 1][w];
+        CT v = fma(-(NREG ? nrow : in[2][w]), south, fma(-in[1][w], west, in[0][w]));
+        if (OP == 1) v = v * in[NL - 1][w];
         res[w] = v;
         west = v;
       }
