@@ -56,11 +56,13 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
-// Streaming geometry of one instance: at most ~2048 blocks of 256 threads.
+// Streaming geometry of one instance: at most ~2048 blocks of 256 threads,
+// each block a multiple of 1024 points (four per thread: the streaming pass
+// kernels take four points per thread per loop trip).
 void stream_geom(int64_t n, int &chunk, int &nblk) {
   int64_t c = (n + 2047) / 2048;
-  c = ((c + 255) / 256) * 256;
-  if (c < 256) c = 256;
+  c = ((c + 1023) / 1024) * 1024;
+  if (c < 1024) c = 1024;
   chunk = (int)c;
   nblk = (int)((n + c - 1) / c);
   if (nblk < 1) nblk = 1;

@@ -49,7 +49,7 @@ struct FastDiv {
 // One instance of a batch.
 struct Inst {
   int32_t nx, ny, n;
-  int32_t chunk;            // points per streaming block (multiple of 256)
+  int32_t chunk;            // points per streaming block (multiple of 1024)
   int64_t off;              // offset of the instance in every batched vector
   int32_t blk0, nblk;       // streaming blocks (blk0 and nblk multiples of 8)
   int32_t strip0, nstrips;  // wavefront strips (for the batch's strip height)
