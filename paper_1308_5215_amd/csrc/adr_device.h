@@ -107,12 +107,19 @@ __device__ __forceinline__ void block_partials(const dd (&v)[NS > 0 ? NS : 1], d
 }
 
 // Single-block fixed-order combine of the per-block partials of one slot.
+// A thread takes partials b, b + BLK, ... in that order; CMB of them are
+// loaded together before they are added, so the loads overlap.
+constexpr int CMB = 8;
 __device__ inline dd combine_dd(const double2 *part, int nblk) {
   __shared__ dd sh[BLK / 64];
   dd acc{0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += BLK) {
-    const double2 q = part[b];
-    acc = dd_add(acc, dd{q.x, q.y});
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += CMB * BLK) {
+    double2 q[CMB];
+#pragma unroll
+    for (int u = 0; u < CMB; ++u) q[u] = part[min(b0 + u * BLK, nblk - 1)];
+#pragma unroll
+    for (int u = 0; u < CMB; ++u)
+      if (b0 + u * BLK < nblk) acc = dd_add(acc, dd{q[u].x, q[u].y});
   }
   dd r = wave_reduce_dd(acc);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
@@ -125,7 +132,14 @@ __device__ inline dd combine_dd(const double2 *part, int nblk) {
 __device__ inline double combine_max(const double2 *part, int nblk) {
   __shared__ double sh[BLK / 64];
   double acc = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += BLK) acc = nanmax(acc, part[b].x);
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += CMB * BLK) {
+    double q[CMB];
+#pragma unroll
+    for (int u = 0; u < CMB; ++u) q[u] = part[min(b0 + u * BLK, nblk - 1)].x;
+#pragma unroll
+    for (int u = 0; u < CMB; ++u)
+      if (b0 + u * BLK < nblk) acc = nanmax(acc, q[u]);
+  }
   double r = wave_reduce_max(acc);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
   __syncthreads();
