@@ -201,11 +201,24 @@ __device__ __forceinline__ double spmv_point_tab(const double *__restrict__ C, c
   const double *Wc = tab, *Ec = tab + nx, *Sr = tab + 2 * nx, *Nr = Sr + ny;
   const Nbr v = load_nbr(x, k, i, j, nx, ny);
   const double xs = v.s, xw = v.w, xe = v.e, xn = v.n;
+  // S and N depend on the row only: when all active lanes of the wave are in
+  // one row they are read once per wave, by scalar loads (the tables are
+  // written by an earlier kernel and only read here).
+  double sr, nr;
+  const int j0 = __builtin_amdgcn_readfirstlane(j);
+  if (__builtin_amdgcn_ballot_w64(j != j0) == 0) {
+    typedef const __attribute__((address_space(4))) double *cdp;
+    sr = ((cdp)Sr)[j0];
+    nr = ((cdp)Nr)[j0];
+  } else {
+    sr = Sr[j];
+    nr = Nr[j];
+  }
   double t = C[k] * v.c;
-  t = fma(Sr[j], xs, t);
+  t = fma(sr, xs, t);
   t = fma(Wc[i], xw, t);
   t = fma(Ec[i], xe, t);
-  t = fma(Nr[j], xn, t);
+  t = fma(nr, xn, t);
   return t;
 }
 
