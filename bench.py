@@ -553,6 +553,20 @@ def main():
         log("  %s: %.1f us  %.0f GB/s" % (name, us, kern[name]["gbs"]))
     dom = max(("lsweep", "usweep"), key=lambda k: kern[k]["avg_us"])
     traffic = traffic_for(dom, "n%d" % n)
+    # the bandwidth a plain element-wise copy reaches here (1 GiB read and
+    # 1 GiB written): a practical ceiling beside the 8 TB/s peak
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    bcp = torch.empty_like(a)
+    bcp.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        bcp.copy_(a)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2 * a.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, bcp
+    log("  copy kernel: %.0f GB/s" % copy_gbs)
     roofline = dict(bound="hbm", kernel=dom, achieved=round(kern[dom]["gbs"], 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(kern[dom]["gbs"] / PEAK_HBM_GBS, 4), traffic=traffic,
                     bytes_per_unknown=BYTES[dom], unknowns_per_launch=N)
@@ -637,6 +651,9 @@ def main():
         "bytes_per_unknown_per_pass": BYTES["iteration"],
         "hbm_gbs_algorithmic": round(algo_gbs, 1),
         "hbm_frac_algorithmic": round(algo_gbs / PEAK_HBM_GBS, 4),
+        "copy_kernel_gbs": round(copy_gbs, 1),
+        "hbm_frac_of_copy_algorithmic": round(algo_gbs / copy_gbs, 4),
+        "roofline_frac_of_copy": round(kern[dom]["gbs"] / copy_gbs, 4),
         # what a plain five-diagonal implementation would have to move per
         # second to keep this pace (392 B per unknown per pass)
         "hbm_gbs_dia_equivalent": round(dia_gbs, 1),
