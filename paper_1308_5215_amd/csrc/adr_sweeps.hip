@@ -170,7 +170,9 @@ struct SweepShape {
   static constexpr int PITCH = W + 2;               // 16-byte aligned rows
   static constexpr int NT = 512;                    // threads per workgroup
   static constexpr int NLD = NT / 64 - 3;           // loader waves
-  static constexpr int LDS_BUDGET = (R <= 15) ? 76 * 1024 : 150 * 1024;   // 2 or 1 workgroups per CU
+  // two workgroups per CU when the ring fits 76 KB with at least four slots
+  // (R = 15, or tiles of at most three arrays), else one with a deeper ring
+  static constexpr int LDS_BUDGET = (R <= 15 || NIN <= 3) ? 76 * 1024 : 150 * 1024;
   static constexpr int OUT_BYTES = 2 * L * PITCH * 8;
   static constexpr int CHUNK_BYTES = NIN * L * PITCH * CTB;
   static constexpr int NC_FIT = (LDS_BUDGET - OUT_BYTES) / CHUNK_BYTES;
