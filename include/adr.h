@@ -196,9 +196,10 @@ adr_status adr_batch_solve(adr_problem *p, double tol, int32_t maxit, const doub
                            double *x_dev, double *hist_l2, double *hist_max, adr_solve_info *info);
 
 /* Sweep-schedule autotuner: times M^{-1} on the problem's right-hand sides
- * for every supported strip height, keeps the fastest and returns it (and the
- * time of one application in ms).  Needs adr_ilu0 / adr_batch_ilu0 first;
- * results do not depend on the choice. */
+ * for every supported schedule -- 15-row strips, and 31-row strips with one
+ * workgroup per CU (deep LDS ring) or two (compact ring) -- keeps the fastest
+ * and returns its strip height (and the time of one application in ms).
+ * Needs adr_ilu0 / adr_batch_ilu0 first; results do not depend on the choice. */
 adr_status adr_autotune(adr_problem *p, int32_t *rows_chosen, double *ms_per_apply);
 
 /* ---------------------------------------------------------------------------
@@ -243,8 +244,20 @@ size_t adr_device_bytes(const adr_problem *p);
 
 /* Sweep geometry: rows per strip (R = 15 or 31) for the wavefront kernels,
  * or 0 for the default (31, also the height a new problem starts with).
- * Results do not depend on it.  For tuning and tests. */
+ * Also returns 31-row strips to the automatic ring choice (two workgroups
+ * per CU once the strips exceed 384, else one).  Results do not depend on
+ * it.  For tuning and tests. */
 adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
+
+/* Ring of the 31-row sweeps: -1 automatic (the default), 0 one workgroup per
+ * CU with a deep LDS ring, 1 two per CU with a four-slot ring (used where a
+ * tile holds at most three arrays: the L sweeps and the table-driven U sweep;
+ * the U sweep reading the diagonals keeps the deep ring).  Results do not
+ * depend on it.  ADR_ERR_ARG for another mode.  For tuning and tests. */
+adr_status adr_set_sweep_ring(adr_problem *p, int32_t mode);
+
+/* The ring the 31-row sweeps use now: 0 deep, 1 compact. */
+int32_t adr_sweep_ring(const adr_problem *p);
 
 /* Stencil tables.  The off-diagonals of the operator of Section 4 are
  * separable: W and E depend only on the column, S and N only on the row

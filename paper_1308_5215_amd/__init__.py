@@ -185,6 +185,14 @@ class Problem(_Workspace):
     def set_sweep_rows(self, rows):
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
 
+    def set_sweep_ring(self, mode):
+        """31-row sweep ring: -1 automatic, 0 deep (one workgroup per CU), 1 compact (two)."""
+        _lib.check(_lib.load().adr_set_sweep_ring(self._h, int(mode)))
+
+    @property
+    def sweep_ring(self):
+        return int(_lib.load().adr_sweep_ring(self._h))
+
     def use_stencil_tables(self, enable=True):
         """Allow (default) or forbid reading S, W, E, N from the separable
         stencil tables instead of the full diagonals (no result changes)."""
@@ -300,6 +308,14 @@ class Batch(_Workspace):
 
     def set_sweep_rows(self, rows):
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
+
+    def set_sweep_ring(self, mode):
+        """31-row sweep ring: -1 automatic, 0 deep (one workgroup per CU), 1 compact (two)."""
+        _lib.check(_lib.load().adr_set_sweep_ring(self._h, int(mode)))
+
+    @property
+    def sweep_ring(self):
+        return int(_lib.load().adr_sweep_ring(self._h))
 
     def use_stencil_tables(self, enable=True):
         _lib.check(_lib.load().adr_use_stencil_tables(self._h, 1 if enable else 0))

@@ -20,7 +20,7 @@ EXPORTS = [
     "adr_get_factors", "adr_spmv", "adr_precond", "adr_lsolve", "adr_usolve", "adr_dot", "adr_device_bytes",
     "adr_set_sweep_rows", "adr_status_str", "adr_last_error", "adr_batch_assemble", "adr_batch_layout",
     "adr_batch_ilu0", "adr_batch_solve", "adr_autotune", "adr_use_stencil_tables", "adr_stencil_tables",
-    "adr_last_call_ms", "adr_workspace_bytes", "adr_bind_workspace",
+    "adr_last_call_ms", "adr_workspace_bytes", "adr_bind_workspace", "adr_set_sweep_ring", "adr_sweep_ring",
     # include/adr_cnn.h
     "adr_cnn_param_count", "adr_cnn_create", "adr_cnn_destroy", "adr_cnn_set_params", "adr_cnn_get_params",
     "adr_cnn_forward", "adr_cnn_gradient", "adr_cnn_adam", "adr_cnn_train_step", "adr_cnn_features",
@@ -76,6 +76,10 @@ def load():
     L.adr_device_bytes.argtypes = [P]
     L.adr_set_sweep_rows.restype = ctypes.c_int
     L.adr_set_sweep_rows.argtypes = [P, i32]
+    L.adr_set_sweep_ring.restype = ctypes.c_int
+    L.adr_set_sweep_ring.argtypes = [P, i32]
+    L.adr_sweep_ring.restype = ctypes.c_int32
+    L.adr_sweep_ring.argtypes = [P]
     L.adr_use_stencil_tables.restype = ctypes.c_int
     L.adr_use_stencil_tables.argtypes = [P, i32]
     L.adr_stencil_tables.restype = ctypes.c_int32

@@ -134,6 +134,7 @@ struct adr_problem {
   Inst *d_inst = nullptr;
   int64_t ntot = 0;            // unknowns over the batch
   int nblk = 0, nstrips = 0, rows = 0, max_ny = 0;
+  int compact = -1;            // 31-row sweep ring: -1 automatic, 0 deep, 1 compact
   size_t bytes = 0;
   // matrix (batched)
   double *S = nullptr, *W = nullptr, *C = nullptr, *E = nullptr, *N = nullptr, *rhs = nullptr;
@@ -179,12 +180,14 @@ struct adr_problem {
   hipGraphExec_t gexec = nullptr;
   double *g_x = nullptr;
   double g_tol = -1;
-  int g_maxit = -1, g_prec = -1, g_rows = -1, g_K = 0, g_tab = -1;
+  int g_maxit = -1, g_prec = -1, g_rows = -1, g_K = 0, g_tab = -1, g_cmp = -1;
 
   SweepSync sync() const { return SweepSync{ticket, handoff, err}; }
   Dia dia() const { return Dia{S, W, C, E, N}; }
   const double *stencil_tab() const { return (has_tab && tab_on) ? tab : nullptr; }
-  BatchGeom geom() const { return BatchGeom{d_inst, count, nblk, nstrips, rows}; }
+  // automatic: compact once the strips exceed 1.5 strips per CU (256 CUs)
+  int ring_compact() const { return compact >= 0 ? compact : (nstrips > 384 ? 1 : 0); }
+  BatchGeom geom() const { return BatchGeom{d_inst, count, nblk, nstrips, rows, ring_compact()}; }
 };
 
 namespace {
@@ -670,8 +673,19 @@ adr_status adr_set_sweep_rows(adr_problem *P, int32_t rows) {
   g_last_error.clear();
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
   if (rows != 0 && rows != 15 && rows != 31) return fail(ADR_ERR_ARG, "rows must be 0, 15 or 31 (got %d)", rows);
+  P->compact = -1;
   return set_rows(P, rows ? rows : default_rows(P->max_ny));
 }
+
+adr_status adr_set_sweep_ring(adr_problem *P, int32_t mode) {
+  g_last_error.clear();
+  if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
+  if (mode < -1 || mode > 1) return fail(ADR_ERR_ARG, "ring mode must be -1, 0 or 1 (got %d)", mode);
+  P->compact = mode;
+  return ADR_OK;
+}
+
+int32_t adr_sweep_ring(const adr_problem *P) { return P ? P->ring_compact() : 0; }
 
 size_t adr_device_bytes(const adr_problem *P) { return P ? P->bytes : 0; }
 
@@ -820,12 +834,15 @@ adr_status adr_autotune(adr_problem *P, int32_t *rows_chosen, double *ms_per_app
   adr_status st = ensure_iter_buffers(P, 0);
   if (st == ADR_OK) st = ensure_events(P);
   if (st != ADR_OK) return st;
-  // time M^{-1} applied to the batch's right-hand sides for every strip height
-  const int cand[] = {15, 31};
-  int best = P->rows;
+  // time M^{-1} applied to the batch's right-hand sides for every strip
+  // schedule: 15-row strips, 31-row strips with the deep ring, with the compact one
+  const int cand[][2] = {{15, -1}, {31, 0}, {31, 1}};
+  int best = P->rows, best_cmp = P->compact;
   float best_ms = -1.f;
   hipEvent_t e0 = P->ev0, e1 = P->ev1;
-  for (int R : cand) {
+  for (const auto &c : cand) {
+    const int R = c[0];
+    P->compact = c[1];
     st = set_rows(P, R);
     if (st != ADR_OK) return st;
     float ms = 0.f;
@@ -846,8 +863,10 @@ adr_status adr_autotune(adr_problem *P, int32_t *rows_chosen, double *ms_per_app
     if (best_ms < 0.f || ms < best_ms) {
       best_ms = ms;
       best = R;
+      best_cmp = c[1];
     }
   }
+  P->compact = best_cmp;
   st = set_rows(P, best);
   if (st != ADR_OK) return st;
   if (rows_chosen) *rows_chosen = best;
@@ -903,7 +922,8 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
   int K = P->ntot >= (1 << 22) ? 4 : (P->ntot >= (1 << 18) ? 8 : 16);
   if (K > maxit && maxit > 0) K = maxit;
   if (!P->gexec || P->g_x != x || P->g_tol != tol || P->g_maxit != maxit || P->g_prec != P->precision ||
-      P->g_rows != P->rows || P->g_K != K || P->g_tab != (P->stencil_tab() != nullptr)) {
+      P->g_rows != P->rows || P->g_K != K || P->g_tab != (P->stencil_tab() != nullptr) ||
+      P->g_cmp != P->ring_compact()) {
     st = build_graph(P, B, K);
     if (st != ADR_OK) return st;
     P->g_x = x;
@@ -911,6 +931,7 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
     P->g_maxit = maxit;
     P->g_prec = P->precision;
     P->g_rows = P->rows;
+    P->g_cmp = P->ring_compact();
     P->g_tab = P->stencil_tab() != nullptr;
   }
   auto all_done = [&]() {

@@ -77,6 +77,7 @@ struct BatchGeom {
   int nblk;           // total streaming blocks
   int nstrips;        // total strips
   int rows;           // strip height R
+  int compact;        // 31-row sweeps: 76 KB ring, two workgroups per CU (see adr_sweeps.hip)
 };
 
 // Single-instance streaming geometry (assembly, diagnostics).

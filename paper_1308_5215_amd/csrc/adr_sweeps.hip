@@ -163,16 +163,17 @@ __device__ __forceinline__ int lds_peek(int *c) {
 }
 __device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local"); }
 
-template <int R, int NIN, int CTB>
+template <int R, int NIN, int CTB, bool CMP>
 struct SweepShape {
   static constexpr int W = 16;                      // columns per chunk
   static constexpr int L = R + 1;                   // tile rows (row 0 = ghost)
   static constexpr int PITCH = W + 2;               // 16-byte aligned rows
   static constexpr int NT = 512;                    // threads per workgroup
   static constexpr int NLD = NT / 64 - 3;           // loader waves
-  // two workgroups per CU when the ring fits 76 KB with at least four slots
-  // (R = 15, or tiles of at most three arrays), else one with a deeper ring
-  static constexpr int LDS_BUDGET = (R <= 15 || NIN <= 3) ? 76 * 1024 : 150 * 1024;
+  // 76 KB (two workgroups per CU) for R = 15 and for compact 31-row strips
+  // (tiles of at most three arrays, four or more slots), else 150 KB (one
+  // workgroup per CU, a deeper ring)
+  static constexpr int LDS_BUDGET = (R <= 15 || CMP) ? 76 * 1024 : 150 * 1024;
   static constexpr int OUT_BYTES = 2 * L * PITCH * 8;
   static constexpr int CHUNK_BYTES = NIN * L * PITCH * CTB;
   static constexpr int NC_FIT = (LDS_BUDGET - OUT_BYTES) / CHUNK_BYTES;
@@ -184,7 +185,7 @@ struct SweepShape {
 
 }  // namespace
 
-template <int R, int OP, int PREC, bool TAB>
+template <int R, int OP, int PREC, bool TAB, bool CMP>
 __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   static_assert(!TAB || OP == 1 || PREC == 0, "the L sweep forms its factors from tables only in FP64");
   using TF = typename std::conditional<PREC == 0, double, float>::type;
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   // a register of that row's lane: its ring tiles hold y, E and invd only.
   constexpr bool NREG = (OP == 1) && TAB;
   constexpr int NL = NREG ? 3 : NIN;   // arrays per ring tile (U: invd last)
-  using Sh = SweepShape<R, NL, (int)sizeof(CT)>;
+  using Sh = SweepShape<R, NL, (int)sizeof(CT), CMP>;
   constexpr int W = Sh::W, L = Sh::L, PITCH = Sh::PITCH, NC = Sh::NC, NT = Sh::NT, NLD = Sh::NLD;
   constexpr int RPP = Sh::RPP, NP = Sh::NP;
   static_assert(L <= 64, "strip too tall");
@@ -609,11 +610,21 @@ hipError_t launch_ilu0(const Dia &A, const BatchGeom &g, Factors64 f64, Factors3
   return hipGetLastError();
 }
 
+// Compact 31-row strips (two workgroups per CU, a four-slot ring) pay off when
+// the strips outnumber the CUs well (batches); a grid whose strips about fill
+// the CUs keeps the deeper ring.  Tiles of four arrays (the U sweep reading
+// the diagonals) always take the deep ring.
 template <int OP, int PREC, bool TAB>
 static hipError_t launch_sweep_t(const SweepParams &p, hipStream_t s) {
+  constexpr bool CAN_CMP = OP == 0 || TAB;   // three arrays per tile
   switch (p.g.rows) {
-    case 15: hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC, TAB>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
-    case 31: hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
+    case 15: hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC, TAB, false>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
+    case 31:
+      if (CAN_CMP && p.g.compact)
+        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, CAN_CMP>), dim3(p.g.nstrips), dim3(512), 0, s, p);
+      else
+        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, false>), dim3(p.g.nstrips), dim3(512), 0, s, p);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

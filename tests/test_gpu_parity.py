@@ -525,6 +525,35 @@ def fields_grf(nx, ny, X, Y, k):
     return fields.gaussian_random_field(nx, ny, X / (nx + 1), Y / (ny + 1), length=0.1, seed=1308, instance=k).ravel()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_factors", "fp32_sweeps"])
+def test_sweep_ring_changes_no_bit(adr, precision):
+    """31-row strips with one workgroup per CU (deep LDS ring) or two (compact
+    ring) give the same preconditioner and the same solve, bit for bit, with
+    the stencil tables and with the full diagonals."""
+    say("sweep ring", precision)
+    prob = adr.assemble(0.05, 1.3, 0.8, 97, 75, 1, 0)
+    prob.ilu0(precision)
+    q = np.random.default_rng(9).standard_normal(97 * 75)
+    for tables in (True, False):
+        prob.use_stencil_tables(tables)
+        got = []
+        for mode in (0, 1):
+            prob.set_sweep_ring(mode)
+            assert prob.sweep_ring == mode
+            z = host(prob.precond(cuda(q)))
+            r = prob.solve(1e-10, 3000)
+            got.append((z, r, host(r.x)))
+        (z0, r0, x0), (z1, r1, x1) = got
+        assert equal(z0, z1)
+        assert r0.status == r1.status and r0.iters == r1.iters
+        assert equal(x0, x1) and equal(r0.hist_l2, r1.hist_l2) and equal(r0.hist_max, r1.hist_max)
+    prob.use_stencil_tables(True)
+    prob.set_sweep_ring(-1)
+    assert prob.sweep_ring == 0   # three strips: the automatic choice is the deep ring
+    with pytest.raises(adr.AdrError):
+        prob.set_sweep_ring(2)
+
+
 def test_batch_autotune_keeps_results(adr):
     say("autotune")
     cols = list(zip(*BATCH[:4]))
@@ -537,3 +566,11 @@ def test_batch_autotune_keeps_results(adr):
     r1 = b.solve(1e-10, 500)
     assert np.array_equal(host(r1.x), x0)
     assert list(r1.iters) == list(r0.iters)
+    # both rings of the 31-row strips, forced
+    for mode in (0, 1):
+        b.set_sweep_rows(31)
+        b.set_sweep_ring(mode)
+        assert b.sweep_ring == mode
+        r2 = b.solve(1e-10, 500)
+        assert np.array_equal(host(r2.x), x0)
+        assert list(r2.iters) == list(r0.iters)
