@@ -70,3 +70,15 @@ def test_amplification_helper():
     """The paper's amplification factor ||r^{k+1}|| / ||r^k|| of a history."""
     import paper_1308_5215_amd as adr
     np.testing.assert_array_equal(adr.amplification([4.0, 2.0, 1.0, 0.25]), [0.5, 0.5, 0.25])
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libadr.so not built")
+def test_schedule_settings_reject_a_missing_problem():
+    """The sweep-schedule settings check their arguments on the host before any
+    device work: a NULL problem is an argument error, and reports no ring."""
+    from paper_1308_5215_amd import _lib
+    L = _lib.load()
+    assert L.adr_set_sweep_ring(None, 1) == _lib.ERR_ARG
+    assert b"NULL" in L.adr_last_error()
+    assert L.adr_set_sweep_rows(None, 31) == _lib.ERR_ARG
+    assert L.adr_sweep_ring(None) == 0
