@@ -186,8 +186,9 @@ def run_batch(args):
                                cols["bc"], field=flat, amp=0.1)
         b.ilu0(args.batch_precision)
         rows, ms = b.autotune()
+        ring = b.sweep_ring
         res = b.solve(tol=args.tol, maxit=args.batch_maxit)
-        return b, rows, ms, res
+        return b, (rows, ring), ms, res
 
     log("batch warmup")
     for _ in range(args.warmup):
@@ -198,7 +199,8 @@ def run_batch(args):
     for _ in range(args.steps):
         b, rows, ms_apply, res = batch_once()
         times.append(res.solve_ms)
-        log("  batch solve %.1f ms, rows %d (autotuned, %.2f ms per M^-1)" % (res.solve_ms, rows, ms_apply))
+        log("  batch solve %.1f ms, rows %d, %s ring (autotuned, %.2f ms per M^-1)" %
+            (res.solve_ms, rows[0], "compact" if rows[1] else "deep", ms_apply))
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
     st = np.asarray(res.status)
@@ -268,7 +270,8 @@ def run_batch(args):
                        "extrapolated": len(sample) != len(inst),
                        "speedup_batched": round(seq_s / batch_s, 2) if batch_s > 0 else None,
                        "max_rel_diff_vs_batched": maxdiff},
-        "sweep_rows": rows,
+        "sweep_rows": rows[0],
+        "sweep_ring": "compact" if rows[1] else "deep",
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
