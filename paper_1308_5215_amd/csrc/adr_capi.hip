@@ -135,6 +135,7 @@ struct adr_problem {
   int64_t ntot = 0;            // unknowns over the batch
   int nblk = 0, nstrips = 0, rows = 0, max_ny = 0;
   int compact = -1;            // 31-row sweep ring: -1 automatic, 0 deep, 1 compact
+  int cus = 256;               // compute units of the device
   size_t bytes = 0;
   // matrix (batched)
   double *S = nullptr, *W = nullptr, *C = nullptr, *E = nullptr, *N = nullptr, *rhs = nullptr;
@@ -185,8 +186,8 @@ struct adr_problem {
   SweepSync sync() const { return SweepSync{ticket, handoff, err}; }
   Dia dia() const { return Dia{S, W, C, E, N}; }
   const double *stencil_tab() const { return (has_tab && tab_on) ? tab : nullptr; }
-  // automatic: compact once the strips exceed 1.5 strips per CU (256 CUs)
-  int ring_compact() const { return compact >= 0 ? compact : (nstrips > 384 ? 1 : 0); }
+  // automatic: compact once the strips exceed 1.5 per CU (384 on 256 CUs)
+  int ring_compact() const { return compact >= 0 ? compact : (2 * nstrips > 3 * cus ? 1 : 0); }
   BatchGeom geom() const { return BatchGeom{d_inst, count, nblk, nstrips, rows, ring_compact()}; }
 };
 
@@ -581,6 +582,8 @@ adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X,
     return st;
   };
   if (hipGetDevice(&P->dev) != hipSuccess) return bail(fail(ADR_ERR_DEVICE, "no HIP device"));
+  if (hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->dev) != hipSuccess || P->cus < 1)
+    return bail(fail(ADR_ERR_DEVICE, "cannot read the device's compute-unit count"));
   P->stream = (hipStream_t)stream;
   P->count = count;
   P->eps.assign(eps, eps + count);
