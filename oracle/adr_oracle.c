@@ -35,7 +35,8 @@ enum {
   OR_BREAKDOWN_RHO = 2,
   OR_OMEGA_ZERO = 3,
   OR_ZERO_PIVOT = 4,
-  OR_NONFINITE = 5
+  OR_NONFINITE = 5,
+  OR_INACCURATE = 6
 };
 
 /* ------------------------------------------------------------------------ */
@@ -146,12 +147,21 @@ void or_forcing(double eps, double X, double Y, int32_t nx, int32_t ny, double *
  * of the appendix), i.e. C += E (resp. N) and rhs -= E dx g_x (resp. N dy g_y);
  * on the corner node the x-edge term is added first.
  * Couplings to boundary nodes are stored as 0.
- * forcing: NULL for the manufactured f; else f = f_man + amp * max|f_man| * g
- * with g = forcing (nx*ny values), the max taken over interior nodes.
+ * Problem data, as the appendix's assembly routines take it (each NULL for
+ * the manufactured problem of Sections 2-3):
+ *   f_user  forcing at every interior node (nx*ny values);
+ *   u_x0    u(0, y_j) (ny values);  u_xX  u(X, y_j), or g_x(y_j) = du/dx for bc = 1;
+ *   u_y0    u(x_i, 0) (nx values);  u_yY  u(x_i, Y), or g_y(x_i) = du/dy for bc = 1.
+ * forcing: NULL, or a perturbation added to the manufactured f:
+ * f = f_man + amp * max|f_man| * g with g = forcing (nx*ny values), the max
+ * taken over interior nodes (ignored when f_user is given).
  * Returns OR_OK or OR_ERR_ARG. */
-int or_assemble(double eps, double X, double Y, int32_t nx, int32_t ny,
-                int32_t scheme, int32_t bc, const double *forcing, double amp,
-                double *S, double *W, double *C, double *E, double *N, double *rhs) {
+int or_assemble_data(double eps, double X, double Y, int32_t nx, int32_t ny,
+                     int32_t scheme, int32_t bc, const double *f_user,
+                     const double *forcing, double amp,
+                     const double *u_x0_user, const double *u_xX_user,
+                     const double *u_y0_user, const double *u_yY_user,
+                     double *S, double *W, double *C, double *E, double *N, double *rhs) {
   if (!(eps > 0.0) || !(X > 0.0) || !(Y > 0.0) || nx < 1 || ny < 1 ||
       (scheme != 0 && scheme != 1) || (bc != 0 && bc != 1))
     return OR_ERR_ARG;
@@ -174,10 +184,21 @@ int or_assemble(double eps, double X, double Y, int32_t nx, int32_t ny,
   or_tables(X, Y, nx, ny, x, y, a, b, ex, ey, eb);
   or_boundary(X, Y, nx, ny, u_x0, u_xX, u_y0, u_yY, g_xX, g_yY);
 
+  /* user boundary data replaces the manufactured values */
+  if (u_x0_user) memcpy(u_x0, u_x0_user, sizeof(double) * (size_t)ny);
+  if (u_xX_user) memcpy(bc == 0 ? u_xX : g_xX, u_xX_user, sizeof(double) * (size_t)ny);
+  if (u_y0_user) memcpy(u_y0, u_y0_user, sizeof(double) * (size_t)nx);
+  if (u_yY_user) memcpy(bc == 0 ? u_yY : g_yY, u_yY_user, sizeof(double) * (size_t)nx);
+
   /* forcing */
-  for (int32_t j = 0; j < ny; ++j)
-    for (int32_t i = 0; i < nx; ++i)
-      rhs[(size_t)j * nx + i] = or_f_point(eps, X, Y, x[i], y[j], a[i], ex[i], ey[j], eb[j]);
+  if (f_user) {
+    memcpy(rhs, f_user, sizeof(double) * n);
+    forcing = NULL;
+  } else {
+    for (int32_t j = 0; j < ny; ++j)
+      for (int32_t i = 0; i < nx; ++i)
+        rhs[(size_t)j * nx + i] = or_f_point(eps, X, Y, x[i], y[j], a[i], ex[i], ey[j], eb[j]);
+  }
   if (forcing) {
     double fmax = 0.0;
     for (size_t k = 0; k < n; ++k) {
@@ -231,6 +252,74 @@ int or_assemble(double eps, double X, double Y, int32_t nx, int32_t ny,
   }
   free(x); free(a); free(ex); free(y); free(b); free(ey); free(eb);
   free(u_x0); free(u_xX); free(g_xX); free(u_y0); free(u_yY); free(g_yY);
+  return OR_OK;
+}
+
+/* The manufactured problem, optionally with a forcing perturbation (see
+ * or_assemble_data). */
+int or_assemble(double eps, double X, double Y, int32_t nx, int32_t ny,
+                int32_t scheme, int32_t bc, const double *forcing, double amp,
+                double *S, double *W, double *C, double *E, double *N, double *rhs) {
+  return or_assemble_data(eps, X, Y, nx, ny, scheme, bc, NULL, forcing, amp, NULL, NULL, NULL, NULL,
+                          S, W, C, E, N, rhs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Instance classification (Section 6.3, mesh Reynolds number).             */
+/* ------------------------------------------------------------------------ */
+
+/* What the discretisation of one instance looks like before it is solved.
+ *   pe_x, pe_y  cell Peclet (mesh Reynolds) numbers max_i a_i dx / eps and
+ *               max_j b_j dy / eps over the interior nodes (Section 6.3: the
+ *               centered scheme stays free of oscillations below 2);
+ *   g_y         X (1 - exp(-Y)) / eps, the integral of b(y)/eps over [0, Y]:
+ *               with Neumann data on x = X, y = Y the closed operator grows
+ *               like exp(g_y) (the paper observes that low eps makes the
+ *               Neumann condition fail, Section 6.1);
+ *   neg_offdiag couplings S, W, E, N between interior unknowns that are < 0
+ *               (none: -A has the sign pattern of an M-matrix);
+ *   nonneg_diag interior points with C >= 0 (the diagonal changes sign, and
+ *               the ILU(0) pivots can pass through zero);
+ *   expect_fail 1 if the solve is expected not to reach a small residual:
+ *               Neumann data with g_y > 20, or a diagonal that is not
+ *               negative everywhere.
+ * Computed from the assembled five diagonals, point by point. */
+typedef struct {
+  double pe_x, pe_y, g_y;
+  int64_t neg_offdiag, nonneg_diag;
+  int32_t expect_fail, pad;
+} or_class;
+
+int or_classify(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme, int32_t bc,
+                or_class *out) {
+  memset(out, 0, sizeof(*out));
+  if (!(eps > 0.0) || !(X > 0.0) || !(Y > 0.0) || nx < 1 || ny < 1 ||
+      (scheme != 0 && scheme != 1) || (bc != 0 && bc != 1))
+    return OR_ERR_ARG;
+  const size_t n = (size_t)nx * (size_t)ny;
+  double *S = malloc(sizeof(double) * n), *W = malloc(sizeof(double) * n), *C = malloc(sizeof(double) * n);
+  double *E = malloc(sizeof(double) * n), *N = malloc(sizeof(double) * n), *r = malloc(sizeof(double) * n);
+  or_assemble(eps, X, Y, nx, ny, scheme, bc, NULL, 0.0, S, W, C, E, N, r);
+  const double dx = X / (double)(nx + 1), dy = Y / (double)(ny + 1);
+  double amax = 0.0, bmax = 0.0;
+  for (int32_t i = 0; i < nx; ++i) {
+    const double xi = (double)(i + 1) * dx;
+    const double a = 1.0 + xi * xi;
+    if (a > amax) amax = a;
+  }
+  for (int32_t j = 0; j < ny; ++j) {
+    const double b = X * exp(-(double)(j + 1) * dy);
+    if (b > bmax) bmax = b;
+  }
+  out->pe_x = amax * dx / eps;
+  out->pe_y = bmax * dy / eps;
+  out->g_y = X * (1.0 - exp(-Y)) / eps;
+  for (size_t k = 0; k < n; ++k) {
+    out->neg_offdiag += (S[k] < 0.0) + (W[k] < 0.0) + (E[k] < 0.0) + (N[k] < 0.0);
+    out->nonneg_diag += (C[k] >= 0.0);
+  }
+  out->expect_fail = (bc == 1 && out->g_y > 20.0) || out->nonneg_diag > 0;
+  free(S); free(W); free(C); free(E); free(N); free(r);
   return OR_OK;
 }
 
@@ -438,29 +527,66 @@ double or_maxabs(int64_t n, const double *x) {
 
 /* Result record of one solve. */
 typedef struct {
-  int32_t status;      /* OR_OK, OR_MAXIT, OR_BREAKDOWN_RHO, OR_OMEGA_ZERO, OR_NONFINITE */
+  int32_t status;      /* OR_OK, OR_MAXIT, OR_BREAKDOWN_RHO, OR_OMEGA_ZERO, OR_NONFINITE, OR_INACCURATE */
   int32_t iters;       /* loop passes started (a half-step exit counts) */
   int32_t hist_len;    /* valid entries of the residual histories */
   int32_t half_step;   /* 1 if the last pass ended on the ||s|| test */
   double bnorm;        /* ||b||_2 */
   double true_relres;  /* ||b - A x||_2 / ||b||_2 at exit (0 when b = 0) */
+  int32_t restarts;    /* restarts from the current iterate (see below) */
+  int32_t pad;
 } or_solve_info;
 
-/* Right-preconditioned BiCGSTAB exactly as the algorithm of Section 5.2 (and
- * its appendix implementation): r0 = b - A x0, r^ = r0; per pass i:
- *   rho = r^.r (fail on 0); p = r (i = 1) or
+/* Apply M^{-1} = U^{-1} L^{-1} (double or single precision substitutions). */
+static void apply_precond(int32_t nx, int32_t ny, const double *lw, const double *ls,
+                          const double *ue, const double *un, const double *invd,
+                          int32_t sweep_f32, const double *q, double *tmp, double *out) {
+  if (sweep_f32) {
+    or_lsolve_f32(nx, ny, lw, ls, q, tmp);
+    or_usolve_f32(nx, ny, ue, un, invd, tmp, out);
+  } else {
+    or_lsolve(nx, ny, lw, ls, q, tmp);
+    or_usolve(nx, ny, ue, un, invd, tmp, out);
+  }
+}
+
+/* e = b - A x by plain subtraction; returns ||e||_2 (double-double dot). */
+static double true_residual(int32_t nx, int32_t ny, const double *S, const double *W,
+                            const double *C, const double *E, const double *N,
+                            const double *b, const double *x, double *tmp, double *e) {
+  const int64_t n = (int64_t)nx * (int64_t)ny;
+  or_spmv(nx, ny, S, W, C, E, N, x, tmp);
+  for (int64_t k = 0; k < n; ++k) e[k] = b[k] - tmp[k];
+  return sqrt(or_dot(n, e, e));
+}
+
+/* Right-preconditioned BiCGSTAB as the algorithm of Section 5.2 (and its
+ * appendix implementation): r0 = b - A x0, r^ = r0; per pass i:
+ *   rho = r^.r (fail on 0); p = r (first pass) or
  *   p = r + beta (p - omega v), beta = (rho_i/rho_{i-1}) (alpha/omega);
  *   M p^ = p; v = A p^; alpha = rho / (r^.v); s = r - alpha v;
- *   if ||s|| small: x += alpha p^, stop;
+ *   if ||s|| small: x += alpha p^, converged;
  *   M z = s; t = A z; omega = (t.s)/(t.t); x += alpha p^ + omega z;
- *   r = s - omega t; record ||r||; stop on convergence, or if omega = 0.
+ *   r = s - omega t; record ||r||; converged if ||r|| small; stop if omega = 0.
  * M = L U with L = I + (lw, ls) and U = diag(1/invd) + (ue, un).
  * Stopping ("small"): ||.||_2 < tol*||b||_2 (abs_tol = 0) or ||.||_2 < tol
  * (abs_tol = 1, the appendix's absolute test).  If ||r0|| already passes the
  * test the solve returns with zero passes.  b = 0 returns x = 0.
+ *
+ * The tests above look at the recursively updated residual, which can drift
+ * away from the true residual b - A x (the paper is silent on this).  With
+ * max_restarts >= 0 a convergence of the recursion is accepted only if the
+ * true residual passes the same test; otherwise, if passes are left
+ * (i < maxit) and fewer than max_restarts restarts were made, the method
+ * starts again from the current iterate as from an initial guess
+ * (r = r^ = b - A x, next pass with p = r), else it stops with OR_MAXIT
+ * (i = maxit) or OR_INACCURATE.  max_restarts < 0 keeps the recursive test
+ * alone (the appendix's behaviour).
+ *
  * Fixed update formulas: p = fma(beta, fma(-omega, v, p), r),
  * s = fma(-alpha, v, r), x = fma(omega, z, fma(alpha, p^, x)),
- * r = fma(-omega, t, s); r0 = b - A x0 by plain subtraction.
+ * r = fma(-omega, t, s); r0 = b - A x0 (and b - A x at a check) by plain
+ * subtraction.
  * sweep_f32 = 1 applies M^{-1} with the single-precision substitutions
  * (or_lsolve_f32 / or_usolve_f32); the factors must then hold float values.
  * x0 may be NULL (zero guess).  hist_l2/hist_max hold maxit+1 entries:
@@ -471,7 +597,7 @@ int or_bicgstab(int32_t nx, int32_t ny,
                 const double *lw, const double *ls, const double *invd,
                 const double *ue, const double *un,
                 const double *b, const double *x0, double tol, int32_t abs_tol, int32_t maxit,
-                int32_t sweep_f32,
+                int32_t sweep_f32, int32_t max_restarts,
                 double *x, double *hist_l2, double *hist_max, or_solve_info *info) {
   const int64_t n = (int64_t)nx * (int64_t)ny;
   memset(info, 0, sizeof(*info));
@@ -485,94 +611,98 @@ int or_bicgstab(int32_t nx, int32_t ny,
   double *ph = calloc((size_t)n, sizeof(double)), *z = calloc((size_t)n, sizeof(double));
   double *yy = calloc((size_t)n, sizeof(double));
   int status = OR_MAXIT;
-  int32_t it = 0, hl = 0;
+  int32_t it = 0, hl = 0, restarts = 0, half = 0;
   const double bnorm = sqrt(or_dot(n, b, b));
   info->bnorm = bnorm;
   if (x0) memcpy(x, x0, sizeof(double) * (size_t)n);
   else memset(x, 0, sizeof(double) * (size_t)n);
   if (bnorm == 0.0) {
     memset(x, 0, sizeof(double) * (size_t)n);
-    if (maxit >= 0 && hist_l2) { hist_l2[0] = 0.0; hist_max[0] = 0.0; }
+    if (hist_l2) { hist_l2[0] = 0.0; hist_max[0] = 0.0; }
     info->status = OR_OK; info->iters = 0; info->hist_len = 1; info->true_relres = 0.0;
     goto done;
   }
   const double thr = abs_tol ? tol : tol * bnorm;
   /* r0 = b - A x0 */
-  or_spmv(nx, ny, S, W, C, E, N, x, v);
-  for (int64_t k = 0; k < n; ++k) r[k] = b[k] - v[k];
+  double rnorm = true_residual(nx, ny, S, W, C, E, N, b, x, v, r);
   memcpy(rh, r, sizeof(double) * (size_t)n);
-  double rnorm = sqrt(or_dot(n, r, r));
   hist_l2[0] = rnorm;
   hist_max[0] = or_maxabs(n, r);
   hl = 1;
   if (!isfinite(rnorm)) { status = OR_NONFINITE; goto finish; }
   if (rnorm < thr) { status = OR_OK; goto finish; }
   double rho = or_dot(n, rh, r), rho_prev = 0.0, alpha = 0.0, omega = 0.0;
+  int fresh = 1;   /* p = r: the first pass and the first pass after a restart */
   for (int32_t i = 1; i <= maxit; ++i) {
     it = i;
     if (!isfinite(rho)) { status = OR_NONFINITE; break; }
     if (rho == 0.0) { status = OR_BREAKDOWN_RHO; break; }
-    if (i == 1) {
+    if (fresh) {
       memcpy(p, r, sizeof(double) * (size_t)n);
     } else {
       const double beta = (rho / rho_prev) * (alpha / omega);
       for (int64_t k = 0; k < n; ++k) p[k] = fma(beta, fma(-omega, v[k], p[k]), r[k]);
     }
-    if (sweep_f32) {
-      or_lsolve_f32(nx, ny, lw, ls, p, yy);
-      or_usolve_f32(nx, ny, ue, un, invd, yy, ph);
-    } else {
-      or_lsolve(nx, ny, lw, ls, p, yy);
-      or_usolve(nx, ny, ue, un, invd, yy, ph);
-    }
+    fresh = 0;
+    apply_precond(nx, ny, lw, ls, ue, un, invd, sweep_f32, p, yy, ph);
     or_spmv(nx, ny, S, W, C, E, N, ph, v);
     alpha = rho / or_dot(n, rh, v);
     if (!isfinite(alpha)) { status = OR_NONFINITE; break; }
     for (int64_t k = 0; k < n; ++k) s[k] = fma(-alpha, v[k], r[k]);
     const double snorm = sqrt(or_dot(n, s, s));
     if (!isfinite(snorm)) { status = OR_NONFINITE; break; }
+    int converged = 0;
     if (snorm < thr) {
       for (int64_t k = 0; k < n; ++k) x[k] = fma(alpha, ph[k], x[k]);
       hist_l2[i] = snorm;
       hist_max[i] = or_maxabs(n, s);
       hl = i + 1;
-      info->half_step = 1;
-      status = OR_OK;
-      break;
-    }
-    if (sweep_f32) {
-      or_lsolve_f32(nx, ny, lw, ls, s, yy);
-      or_usolve_f32(nx, ny, ue, un, invd, yy, z);
+      half = 1;
+      converged = 1;
     } else {
-      or_lsolve(nx, ny, lw, ls, s, yy);
-      or_usolve(nx, ny, ue, un, invd, yy, z);
+      apply_precond(nx, ny, lw, ls, ue, un, invd, sweep_f32, s, yy, z);
+      or_spmv(nx, ny, S, W, C, E, N, z, t);
+      const double ts = or_dot(n, t, s), tt = or_dot(n, t, t);
+      omega = ts / tt;
+      if (!isfinite(omega)) { status = OR_NONFINITE; break; }
+      for (int64_t k = 0; k < n; ++k) {
+        x[k] = fma(omega, z[k], fma(alpha, ph[k], x[k]));
+        r[k] = fma(-omega, t[k], s[k]);
+      }
+      rnorm = sqrt(or_dot(n, r, r));
+      hist_l2[i] = rnorm;
+      hist_max[i] = or_maxabs(n, r);
+      hl = i + 1;
+      rho_prev = rho;
+      rho = or_dot(n, rh, r);
+      if (!isfinite(rnorm)) { status = OR_NONFINITE; break; }
+      if (rnorm < thr) converged = 1;
+      else if (omega == 0.0) { status = OR_OMEGA_ZERO; break; }
     }
-    or_spmv(nx, ny, S, W, C, E, N, z, t);
-    const double ts = or_dot(n, t, s), tt = or_dot(n, t, t);
-    omega = ts / tt;
-    if (!isfinite(omega)) { status = OR_NONFINITE; break; }
-    for (int64_t k = 0; k < n; ++k) {
-      x[k] = fma(omega, z[k], fma(alpha, ph[k], x[k]));
-      r[k] = fma(-omega, t[k], s[k]);
+    if (converged) {
+      if (max_restarts < 0) { status = OR_OK; break; }
+      /* the recursion converged: check the true residual */
+      const double te = true_residual(nx, ny, S, W, C, E, N, b, x, v, t);
+      if (te < thr) { status = OR_OK; break; }
+      if (i >= maxit) { status = OR_MAXIT; break; }
+      if (restarts >= max_restarts) { status = OR_INACCURATE; break; }
+      /* restart from the current iterate: r = r^ = b - A x */
+      ++restarts;
+      half = 0;
+      memcpy(r, t, sizeof(double) * (size_t)n);
+      memcpy(rh, t, sizeof(double) * (size_t)n);
+      rho = or_dot(n, rh, r);
+      fresh = 1;
     }
-    rnorm = sqrt(or_dot(n, r, r));
-    hist_l2[i] = rnorm;
-    hist_max[i] = or_maxabs(n, r);
-    hl = i + 1;
-    rho_prev = rho;
-    rho = or_dot(n, rh, r);
-    if (!isfinite(rnorm)) { status = OR_NONFINITE; break; }
-    if (rnorm < thr) { status = OR_OK; break; }
-    if (omega == 0.0) { status = OR_OMEGA_ZERO; break; }
   }
 finish:
   info->status = status;
   info->iters = it;
   info->hist_len = hl;
+  info->half_step = half;
+  info->restarts = restarts;
   /* true residual at exit */
-  or_spmv(nx, ny, S, W, C, E, N, x, v);
-  for (int64_t k = 0; k < n; ++k) t[k] = b[k] - v[k];
-  info->true_relres = sqrt(or_dot(n, t, t)) / bnorm;
+  info->true_relres = true_residual(nx, ny, S, W, C, E, N, b, x, v, t) / bnorm;
 done:
   free(r); free(rh); free(p); free(v); free(s); free(t); free(ph); free(z); free(yy);
   return info->status;

@@ -14,7 +14,8 @@ from . import build as _build
 
 _lib = None
 
-OK, ERR_ARG, MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE = 0, -1, 1, 2, 3, 4, 5
+OK, ERR_ARG, MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE, INACCURATE = 0, -1, 1, 2, 3, 4, 5, 6
+MAX_RESTARTS = 8   # default restarts from the current iterate (see or_bicgstab)
 UPWIND, CENTERED = 0, 1
 DIRICHLET, NEUMANN = 0, 1
 
@@ -24,7 +25,14 @@ _D = ctypes.POINTER(ctypes.c_double)
 class _Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("hist_len", ctypes.c_int32), ("half_step", ctypes.c_int32),
-                ("bnorm", ctypes.c_double), ("true_relres", ctypes.c_double)]
+                ("bnorm", ctypes.c_double), ("true_relres", ctypes.c_double),
+                ("restarts", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class _Class(ctypes.Structure):
+    _fields_ = [("pe_x", ctypes.c_double), ("pe_y", ctypes.c_double), ("g_y", ctypes.c_double),
+                ("neg_offdiag", ctypes.c_int64), ("nonneg_diag", ctypes.c_int64),
+                ("expect_fail", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 def lib():
@@ -45,6 +53,10 @@ def lib():
         L.or_forcing.argtypes = [f64, f64, f64, i32, i32, _D]
         L.or_assemble.restype = ctypes.c_int
         L.or_assemble.argtypes = [f64, f64, f64, i32, i32, i32, i32, _D, f64] + [_D] * 6
+        L.or_assemble_data.restype = ctypes.c_int
+        L.or_assemble_data.argtypes = [f64, f64, f64, i32, i32, i32, i32, _D, _D, f64] + [_D] * 10
+        L.or_classify.restype = ctypes.c_int
+        L.or_classify.argtypes = [f64, f64, f64, i32, i32, i32, i32, ctypes.POINTER(_Class)]
         L.or_spmv.argtypes = [i32, i32] + [_D] * 7
         L.or_ilu0.restype = ctypes.c_int
         L.or_ilu0.argtypes = [i32, i32] + [_D] * 8 + [ctypes.POINTER(i64)]
@@ -55,7 +67,7 @@ def lib():
         L.or_maxabs.restype = f64
         L.or_maxabs.argtypes = [i64, _D]
         L.or_bicgstab.restype = ctypes.c_int
-        L.or_bicgstab.argtypes = ([i32, i32] + [_D] * 10 + [_D, _D, f64, i32, i32, i32, _D, _D, _D,
+        L.or_bicgstab.argtypes = ([i32, i32] + [_D] * 10 + [_D, _D, f64, i32, i32, i32, i32, _D, _D, _D,
                                                              ctypes.POINTER(_Info)])
         L.or_lsolve_f32.argtypes = [i32, i32] + [_D] * 4
         L.or_usolve_f32.argtypes = [i32, i32] + [_D] * 5
@@ -145,6 +157,43 @@ def assemble(eps, X, Y, nx, ny, scheme=UPWIND, bc=DIRICHLET, field=None, amp=0.0
     return Problem(eps, X, Y, nx, ny, scheme, bc, *arrs)
 
 
+def assemble_data(eps, X, Y, nx, ny, scheme=UPWIND, bc=DIRICHLET, f=None, u_x0=None, u_xX=None,
+                  u_y0=None, u_yY=None):
+    """Assembly from user problem data (see ``or_assemble_data``): f (nx*ny),
+    u_x0, u_xX (ny each), u_y0, u_yY (nx each); for bc = NEUMANN u_xX and u_yY
+    are the normal derivatives.  None = the manufactured value."""
+    n = nx * ny
+    arrs = [np.zeros(n) for _ in range(6)]
+    conv = lambda a, m: None if a is None else _f64(a).ravel()
+    data = [conv(f, n), conv(u_x0, ny), conv(u_xX, ny), conv(u_y0, nx), conv(u_yY, nx)]
+    for a, m in zip(data, (n, ny, ny, nx, nx)):
+        assert a is None or a.size == m
+    rc = lib().or_assemble_data(float(eps), float(X), float(Y), int(nx), int(ny), int(scheme), int(bc),
+                                _p(data[0]), None, 0.0, *[_p(a) for a in data[1:]], *[_p(a) for a in arrs])
+    if rc != OK:
+        raise ValueError("or_assemble_data rejected its arguments (status %d)" % rc)
+    return Problem(eps, X, Y, nx, ny, scheme, bc, *arrs)
+
+
+@dataclass
+class Classification:
+    pe_x: float
+    pe_y: float
+    g_y: float
+    neg_offdiag: int
+    nonneg_diag: int
+    expect_fail: bool
+
+
+def classify(eps, X, Y, nx, ny, scheme=UPWIND, bc=DIRICHLET):
+    c = _Class()
+    rc = lib().or_classify(float(eps), float(X), float(Y), int(nx), int(ny), int(scheme), int(bc),
+                           ctypes.byref(c))
+    if rc != OK:
+        raise ValueError("or_classify rejected its arguments (status %d)" % rc)
+    return Classification(c.pe_x, c.pe_y, c.g_y, c.neg_offdiag, c.nonneg_diag, bool(c.expect_fail))
+
+
 def spmv(P, x):
     x = _f64(x)
     v = np.zeros(P.n)
@@ -228,9 +277,15 @@ class Solve:
     half_step: bool
     bnorm: float
     true_relres: float
+    restarts: int = 0
 
 
-def bicgstab(P, F, tol=1e-10, maxit=1000, x0=None, abs_tol=False, b=None, sweep_f32=False):
+def bicgstab(P, F, tol=1e-10, maxit=1000, x0=None, abs_tol=False, b=None, sweep_f32=False,
+             max_restarts=MAX_RESTARTS):
+    """BiCGSTAB of Section 5.2 (``or_bicgstab``).  max_restarts < 0 keeps the
+    recursive stopping test alone (the appendix's solver); otherwise a
+    convergence of the recursion is confirmed on the true residual, with up to
+    max_restarts restarts from the current iterate."""
     rhs = P.rhs if b is None else _f64(b)
     x = np.zeros(P.n)
     h2 = np.zeros(maxit + 1)
@@ -240,10 +295,10 @@ def bicgstab(P, F, tol=1e-10, maxit=1000, x0=None, abs_tol=False, b=None, sweep_
     lib().or_bicgstab(P.nx, P.ny, _p(P.S), _p(P.W), _p(P.C), _p(P.E), _p(P.N),
                       _p(F.lw), _p(F.ls), _p(F.invd), _p(F.ue), _p(F.un),
                       _p(rhs), _p(x0p), float(tol), int(bool(abs_tol)), int(maxit), int(bool(sweep_f32)),
-                      _p(x), _p(h2), _p(hm), ctypes.byref(info))
+                      int(max_restarts), _p(x), _p(h2), _p(hm), ctypes.byref(info))
     hl = info.hist_len
     return Solve(x, h2[:hl].copy(), hm[:hl].copy(), info.status, info.iters,
-                 bool(info.half_step), info.bnorm, info.true_relres)
+                 bool(info.half_step), info.bnorm, info.true_relres, info.restarts)
 
 
 def max_error(P, sol):

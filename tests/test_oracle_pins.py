@@ -367,7 +367,7 @@ def test_table_6_2_iterations_with_the_appendix_settings(orc, tables):
     for name, sch in SCHEME.items():
         for eps, printed in zip(t["eps"], t[name + "_iterations"]):
             P = orc.assemble(eps, t["X"], t["Y"], nx, nx, sch, core.DIRICHLET)
-            s = orc.bicgstab(P, dense.truncated_lu(P), tol=st["abs_tol"], abs_tol=True, maxit=1000,
+            s = orc.bicgstab(P, dense.truncated_lu(P), tol=st["abs_tol"], abs_tol=True, maxit=1000, max_restarts=-1,
                              x0=np.full(P.n, st["x0_preconditioned"]))
             if printed is None:  # "NC": not converged within 1000 passes
                 assert s.status == core.MAXIT
@@ -383,7 +383,7 @@ def test_table_6_1_iterations_with_the_appendix_settings(orc, tables):
     nx = t["m"] - 1
     for case in t["cases"]:
         P = orc.assemble(t["eps"], t["X"], t["Y"], nx, nx, SCHEME[case["scheme"]], BC[case["bc"]])
-        s = orc.bicgstab(P, dense.truncated_lu(P), tol=st["abs_tol"], abs_tol=True, maxit=1000,
+        s = orc.bicgstab(P, dense.truncated_lu(P), tol=st["abs_tol"], abs_tol=True, maxit=1000, max_restarts=-1,
                          x0=np.full(P.n, st["x0_preconditioned"]))
         assert s.status == core.OK and abs(s.iters - case["iterations"]) <= 3, (case, s.iters)
         assert agrees_to_printed(orc.max_error(P, s.x), case["max_error"])
@@ -397,11 +397,11 @@ def test_table_6_5_and_6_8_iterations_other_preconditioners(orc, tables):
     st = tables["solver_settings"]
     for bcname, bc in BC.items():
         P = orc.assemble(t5["eps"], t5["X"], t5["Y"], t5["m"] - 1, t5["m"] - 1, core.UPWIND, bc)
-        s = orc.bicgstab(P, dense.split_lu(P), tol=st["abs_tol"], abs_tol=True, maxit=5000,
+        s = orc.bicgstab(P, dense.split_lu(P), tol=st["abs_tol"], abs_tol=True, maxit=5000, max_restarts=-1,
                          x0=np.full(P.n, st["x0_preconditioned"]))
         assert s.status == core.OK
         assert abs(s.iters - t5["split_lu_bicgstab_iterations"][bcname]) <= 5, (bcname, s.iters)
-        s = orc.bicgstab(P, dense.identity(P), tol=st["abs_tol"], abs_tol=True, maxit=5000,
+        s = orc.bicgstab(P, dense.identity(P), tol=st["abs_tol"], abs_tol=True, maxit=5000, max_restarts=-1,
                          x0=np.full(P.n, st["x0_unpreconditioned"]))
         assert s.status == core.OK
         assert abs(s.iters - t5["unpreconditioned_iterations"][bcname]) <= 5, (bcname, s.iters)
@@ -410,7 +410,7 @@ def test_table_6_5_and_6_8_iterations_other_preconditioners(orc, tables):
     for name, sch in SCHEME.items():
         for m, printed in zip(t8["m"], t8[name + "_iterations"]):
             P = orc.assemble(t8["eps"], t8["X"], t8["Y"], m - 1, m - 1, sch, core.DIRICHLET)
-            s = orc.bicgstab(P, dense.identity(P), tol=st["abs_tol"], abs_tol=True, maxit=1000,
+            s = orc.bicgstab(P, dense.identity(P), tol=st["abs_tol"], abs_tol=True, maxit=1000, max_restarts=-1,
                              x0=np.full(P.n, st["x0_unpreconditioned"]))
             assert s.status == core.OK and abs(s.iters - printed) <= 5, (name, m, s.iters)
 
