@@ -48,7 +48,10 @@ typedef enum {
   ADR_BREAKDOWN_RHO = 2,  /* rho = r^.r = 0 at the start of a pass          */
   ADR_OMEGA_ZERO = 3,     /* omega = 0 (the method's own stop)              */
   ADR_ZERO_PIVOT = 4,     /* ILU(0) met a zero or non-finite pivot          */
-  ADR_NONFINITE = 5       /* a scalar of the iteration became Inf or NaN    */
+  ADR_NONFINITE = 5,      /* a scalar of the iteration became Inf or NaN    */
+  ADR_INACCURATE = 6      /* the recursively updated residual passed the
+                             stopping test but the true residual b - A x did
+                             not, and the restarts allowed are used up        */
 } adr_status;
 
 typedef enum {
@@ -83,6 +86,8 @@ typedef struct {
   double bnorm;         /* ||b||_2                                               */
   double true_relres;   /* ||b - A x||_2 / ||b||_2 recomputed at exit            */
   double solve_ms;      /* device time of the iteration (events on the stream)  */
+  int32_t restarts;     /* restarts from the current iterate (see the solve)    */
+  int32_t pad;
 } adr_solve_info;
 
 /* ---------------------------------------------------------------------------
@@ -139,6 +144,15 @@ adr_status adr_ilu0(adr_problem *p, int32_t precision, int64_t *bad_index);
  * Inner products are double-double accumulations rounded once to FP64, so the
  * result does not depend on the summation order.  If ||r0|| already passes
  * the test no pass is made; b = 0 gives x = 0.
+ * True residual: the tests above read the recursively updated residual, which
+ * can drift from b - A x (the paper does not address this).  A solve is
+ * reported ADR_OK only if ||b - A x||_2 < tol ||b||_2 too: when the recursion
+ * converges the next pass slot recomputes e = b - A x; if e passes, the solve
+ * stops OK; otherwise, with passes left and fewer than max_restarts restarts
+ * made (adr_set_max_restarts, default 8), the method restarts from the
+ * current x as from an initial guess (r = r^ = p = e, and that slot is the
+ * first pass of the restart); with no pass left the status is ADR_MAXIT,
+ * with no restart left ADR_INACCURATE.
  * x0_dev: initial guess (device, nx*ny) or NULL for zero.
  * x_dev:  output (device, nx*ny); may equal x0_dev.
  * hist_l2_host, hist_max_host: NULL or host arrays of maxit+1 entries:
@@ -146,13 +160,84 @@ adr_status adr_ilu0(adr_problem *p, int32_t precision, int64_t *bad_index);
  *   residual), or ||s|| at a half-step exit; 2-norm and max-norm.
  * info: optional summary.  tol >= 0, maxit >= 0.
  * Returns the solve status (ADR_OK, ADR_MAXIT, ADR_BREAKDOWN_RHO,
- * ADR_OMEGA_ZERO, ADR_NONFINITE) or a call error; x_dev holds the last
- * iterate in every outcome.
+ * ADR_OMEGA_ZERO, ADR_NONFINITE, ADR_INACCURATE) or a call error; x_dev holds
+ * the last iterate in every outcome.
  * ------------------------------------------------------------------------- */
 adr_status adr_bicgstab_solve(adr_problem *p, double tol, int32_t maxit,
                               const double *x0_dev, double *x_dev,
                               double *hist_l2_host, double *hist_max_host,
                               adr_solve_info *info);
+
+/* Restarts allowed by the true-residual confirmation of a solve (above):
+ * n >= 0 restarts (default 8), or -1 to accept the recursive residual's test
+ * alone, as the algorithm of Section 5.2 and the appendix's solver do.
+ * ADR_ERR_ARG for n < -1. */
+adr_status adr_set_max_restarts(adr_problem *p, int32_t n);
+
+/* ---------------------------------------------------------------------------
+ * adr_assemble_data -- Section 4 assembly from the caller's problem data, as
+ * the paper's assembly routines take it (forcing f and the boundary data of
+ * the four sides), with the paper's input rule: each item is either absent
+ * (NULL pointer, length 0: the manufactured value of Sections 2-3), a single
+ * value used at every node (length 1), or one value per node (length nx*ny
+ * for f, ny for the x-sides, nx for the y-sides); any other length is
+ * ADR_ERR_ARG.
+ *   f     forcing at the interior nodes (k = j*nx + i);
+ *   u_x0  u(0, y_j);   u_xX  u(X, y_j), or du/dx(X, y_j) with ADR_BC_NEUMANN_XY;
+ *   u_y0  u(x_i, 0);   u_yY  u(x_i, Y), or du/dy(x_i, Y) with ADR_BC_NEUMANN_XY.
+ * f_on_device = 1: f is device memory (length nx*ny only); the edge arrays
+ * are host memory.  Everything else is as adr_assemble (stencils, the
+ * Neumann closure, errors, the handle).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const double *f;    int64_t f_len;
+  const double *u_x0; int64_t u_x0_len;
+  const double *u_xX; int64_t u_xX_len;
+  const double *u_y0; int64_t u_y0_len;
+  const double *u_yY; int64_t u_yY_len;
+  int32_t f_on_device;
+  int32_t pad;
+} adr_problem_data;
+
+adr_status adr_assemble_data(double eps, double X, double Y, int32_t nx, int32_t ny,
+                             int32_t scheme, int32_t bc, const adr_problem_data *data,
+                             void *stream, adr_problem **out);
+
+/* ---------------------------------------------------------------------------
+ * adr_max_error -- the discretisation error of a solution (Sections 6.1-6.8):
+ * max over all (nx+2) x (ny+2) grid nodes of |U - u_exact|, with
+ * u_exact = exp(-x/X) (1 - exp(-y/Y)) y and U the solution x_dev at the
+ * interior nodes, the exact u on Dirichlet sides, and on the Neumann sides
+ * of ADR_BC_NEUMANN_XY the one-sided closure U(X, y) = U(x_nx, y) + dx g_x(y),
+ * U(x, Y) = U(x, y_ny) + dy g_y(x) (corner from the x-direction), as the
+ * paper's Neumann drivers reconstruct them.  Meaningful for the manufactured
+ * problem.  x_dev: a (batched) device vector; err_host: one double per
+ * instance.
+ * ------------------------------------------------------------------------- */
+adr_status adr_max_error(adr_problem *p, const double *x_dev, double *err_host);
+
+/* ---------------------------------------------------------------------------
+ * adr_classify -- what an instance's discretisation looks like before it is
+ * solved (Section 6.3, mesh Reynolds number; the Neumann failures noted in
+ * Section 6.1).  Host-only, no device work.
+ *   pe_x, pe_y   cell Peclet numbers max_i a_i dx / eps, max_j b_j dy / eps;
+ *   g_y          X (1 - exp(-Y)) / eps, the integral of b / eps over y: the
+ *                Neumann-closed operator grows like exp(g_y);
+ *   neg_offdiag  couplings between interior unknowns that are negative;
+ *   nonneg_diag  unknowns whose diagonal C is >= 0 (sign change: ILU(0)
+ *                pivots can pass through zero);
+ *   expect_fail  1 if the solve is not expected to reach a small residual:
+ *                Neumann data with g_y > 20, or nonneg_diag > 0.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double pe_x, pe_y, g_y;
+  int64_t neg_offdiag, nonneg_diag;
+  int32_t expect_fail;
+  int32_t pad;
+} adr_instance_class;
+
+adr_status adr_classify(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme,
+                        int32_t bc, adr_instance_class *out);
 
 /* Release every device resource of the problem (NULL is a no-op). */
 void adr_destroy(adr_problem *p);
@@ -176,6 +261,13 @@ adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X,
                               const int32_t *nx, const int32_t *ny, const int32_t *scheme,
                               const int32_t *bc, const double *field_dev, double amp,
                               void *stream, adr_problem **out);
+
+/* The same from each instance's own problem data (adr_assemble_data);
+ * data: `count` records, or NULL for the manufactured problems. */
+adr_status adr_batch_assemble_data(int32_t count, const double *eps, const double *X, const double *Y,
+                                   const int32_t *nx, const int32_t *ny, const int32_t *scheme,
+                                   const int32_t *bc, const adr_problem_data *data,
+                                   void *stream, adr_problem **out);
 
 /* Number of instances and their offsets (count + 1 entries; the last is the
  * total length of a batched vector).  Either output may be NULL. */
@@ -238,6 +330,11 @@ adr_status adr_usolve(adr_problem *p, const double *y_dev, double *z_dev);
  * FP64, written to *out (host). */
 adr_status adr_dot(const double *x_dev, const double *y_dev, int64_t n, void *stream,
                    double *out);
+
+/* Streaming copy dst[k] = src[k], k < n (device vectors, stream as in
+ * adr_dot): a plain HBM-bound kernel, the practical bandwidth reference for
+ * the roofline figures.  Synchronous on return. */
+adr_status adr_stream_copy(const double *src_dev, double *dst_dev, int64_t n, void *stream);
 
 /* Bytes of device memory the problem holds (after ilu0 / solve buffers). */
 size_t adr_device_bytes(const adr_problem *p);

@@ -16,12 +16,13 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib
-from ._lib import (OK, MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE, UPWIND, CENTERED,
+from ._lib import (OK, MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE, INACCURATE, UPWIND, CENTERED,
                    DIRICHLET, NEUMANN_XY, FP64, FP32_FACTORS, FP32_SWEEPS, AdrError)
 
-__all__ = ["assemble", "assemble_batch", "WarmStartNet", "cnn_param_count", "Problem", "Batch", "SolveResult", "BatchResult", "dot", "AdrError", "OK", "MAXIT", "BREAKDOWN_RHO",
-           "OMEGA_ZERO", "ZERO_PIVOT", "NONFINITE", "UPWIND", "CENTERED", "DIRICHLET", "NEUMANN_XY",
-           "FP64", "FP32_FACTORS", "FP32_SWEEPS"]
+__all__ = ["assemble", "assemble_batch", "solve", "classify", "stream_copy", "amplification", "WarmStartNet",
+           "cnn_param_count", "Problem", "Batch", "SolveResult", "BatchResult", "InstanceClass", "dot", "AdrError",
+           "OK", "MAXIT", "BREAKDOWN_RHO", "OMEGA_ZERO", "ZERO_PIVOT", "NONFINITE", "INACCURATE", "UPWIND",
+           "CENTERED", "DIRICHLET", "NEUMANN_XY", "FP64", "FP32_FACTORS", "FP32_SWEEPS"]
 
 _SCHEMES = {"upwind": UPWIND, "hybrid": UPWIND, "centered": CENTERED, UPWIND: UPWIND, CENTERED: CENTERED}
 _BCS = {"dirichlet": DIRICHLET, "neumann": NEUMANN_XY, DIRICHLET: DIRICHLET, NEUMANN_XY: NEUMANN_XY}
@@ -66,6 +67,7 @@ class SolveResult:
     bnorm: float
     true_relres: float
     solve_ms: float
+    restarts: int = 0
 
     @property
     def amplification(self):
@@ -137,7 +139,18 @@ class Problem(_Workspace):
                                                         _host_ptr(h2), _host_ptr(hm), ctypes.byref(info)))
         hl = info.hist_len
         return SolveResult(x, st, info.iters, bool(info.half_step), h2[:hl].copy(), hm[:hl].copy(),
-                           info.bnorm, info.true_relres, info.solve_ms)
+                           info.bnorm, info.true_relres, info.solve_ms, info.restarts)
+
+    def set_max_restarts(self, n):
+        """Restarts allowed by the true-residual confirmation (default 8;
+        -1: the recursive residual's test alone)."""
+        _lib.check(_lib.load().adr_set_max_restarts(self._h, int(n)))
+
+    def max_error(self, x):
+        """max |U - u_exact| over all grid nodes (adr_max_error)."""
+        out = np.zeros(1)
+        _lib.check(_lib.load().adr_max_error(self._h, _dev_f64(x, self.n, "x"), _host_ptr(out)))
+        return float(out[0])
 
     # -- inspection and single steps --
     def get_dia(self):
@@ -214,19 +227,89 @@ class Problem(_Workspace):
         return int(_lib.load().adr_device_bytes(self._h))
 
 
-def assemble(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet", field=None, amp=0.0, stream=None):
+def _problem_data(f, u_x0, u_xX, u_y0, u_yY, keep):
+    """adr_problem_data from Python values: None (manufactured), a scalar
+    (broadcast), a host array, or (f only) a CUDA float64 tensor.  Arrays
+    are kept alive in `keep` for the duration of the call."""
+    torch = _torch()
+    d = _lib.ProblemData()
+
+    def host(v):
+        a = np.ascontiguousarray(np.atleast_1d(np.asarray(v, dtype=np.float64)).ravel())
+        keep.append(a)
+        return ctypes.c_void_p(a.ctypes.data), a.size
+
+    if f is not None:
+        if isinstance(f, torch.Tensor) and f.is_cuda:
+            if f.dtype != torch.float64 or not f.is_contiguous():
+                raise TypeError("f must be a contiguous CUDA float64 tensor")
+            keep.append(f)
+            d.f, d.f_len, d.f_on_device = ctypes.c_void_p(f.data_ptr()), f.numel(), 1
+        else:
+            d.f, d.f_len = host(f)
+    for name, v in (("u_x0", u_x0), ("u_xX", u_xX), ("u_y0", u_y0), ("u_yY", u_yY)):
+        if v is not None:
+            ptr, ln = host(v)
+            setattr(d, name, ptr)
+            setattr(d, name + "_len", ln)
+    return d
+
+
+def assemble(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet", field=None, amp=0.0, stream=None,
+             f=None, u_x0=None, u_xX=None, u_y0=None, u_yY=None):
     """Section 4 assembly on the device; see adr_assemble in include/adr.h.
     field: optional CUDA float64 tensor (nx*ny) added to the manufactured
-    forcing with amplitude amp * max|f_man|."""
-    torch = _torch()
+    forcing with amplitude amp * max|f_man|.
+    f, u_x0, u_xX, u_y0, u_yY: the caller's forcing and boundary data
+    (adr_assemble_data; for Neumann sides u_xX / u_yY are the normal
+    derivatives): each None (manufactured), a scalar, or an array (f may be a
+    CUDA tensor)."""
     L = _lib.load()
     sch, b = _SCHEMES[scheme], _BCS[bc]
-    fp = None if field is None else _dev_f64(field, int(nx) * int(ny), "field")
     sh = _stream_handle(stream)
     h = ctypes.c_void_p()
-    _lib.check(L.adr_assemble(float(eps), float(X), float(Y), int(nx), int(ny), sch, b, fp, float(amp),
-                              sh, ctypes.byref(h)))
+    if any(v is not None for v in (f, u_x0, u_xX, u_y0, u_yY)):
+        if field is not None:
+            raise ValueError("give either field/amp or the problem data f, u_x0, ...")
+        keep = []
+        d = _problem_data(f, u_x0, u_xX, u_y0, u_yY, keep)
+        _lib.check(L.adr_assemble_data(float(eps), float(X), float(Y), int(nx), int(ny), sch, b, ctypes.byref(d),
+                                       sh, ctypes.byref(h)))
+    else:
+        fp = None if field is None else _dev_f64(field, int(nx) * int(ny), "field")
+        _lib.check(L.adr_assemble(float(eps), float(X), float(Y), int(nx), int(ny), sch, b, fp, float(amp),
+                                  sh, ctypes.byref(h)))
     return Problem(h, float(eps), float(X), float(Y), int(nx), int(ny), sch, b, stream)
+
+
+@dataclass
+class InstanceClass:
+    """adr_classify: cell Peclet numbers, the Neumann growth exponent g_y,
+    counts of negative couplings and of non-negative diagonal entries, and
+    whether the solve is expected to fail."""
+    pe_x: float
+    pe_y: float
+    g_y: float
+    neg_offdiag: int
+    nonneg_diag: int
+    expect_fail: bool
+
+
+def classify(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet"):
+    """What an instance's discretisation looks like before it is solved
+    (adr_classify; Section 6.3 mesh Reynolds number)."""
+    c = _lib.InstanceClass()
+    _lib.check(_lib.load().adr_classify(float(eps), float(X), float(Y), int(nx), int(ny), _SCHEMES[scheme],
+                                        _BCS[bc], ctypes.byref(c)))
+    return InstanceClass(c.pe_x, c.pe_y, c.g_y, c.neg_offdiag, c.nonneg_diag, bool(c.expect_fail))
+
+
+def stream_copy(src, dst, stream=None):
+    """dst = src with the library's streaming copy kernel (adr_stream_copy)."""
+    n = src.numel()
+    _lib.check(_lib.load().adr_stream_copy(_dev_f64(src, n, "src"), _dev_f64(dst, n, "dst"), n,
+                                           _stream_handle(stream)))
+    return dst
 
 
 def solve(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet", tol=1e-10, maxit=1000, precision="fp64",
@@ -260,6 +343,7 @@ class BatchResult:
     true_relres: np.ndarray
     solve_ms: float
     overall: int           # adr_batch_solve's return value
+    restarts: np.ndarray = None
 
 
 class Batch(_Workspace):
@@ -346,7 +430,16 @@ class Batch(_Workspace):
             [h2[k, :info[k].hist_len].copy() for k in range(self.count)],
             [hm[k, :info[k].hist_len].copy() for k in range(self.count)],
             np.array([i.bnorm for i in info]), np.array([i.true_relres for i in info]),
-            info[0].solve_ms if self.count else 0.0, st)
+            info[0].solve_ms if self.count else 0.0, st, np.array([i.restarts for i in info]))
+
+    def set_max_restarts(self, n):
+        _lib.check(_lib.load().adr_set_max_restarts(self._h, int(n)))
+
+    def max_error(self, x):
+        """Per instance max |U - u_exact| over all grid nodes (adr_max_error)."""
+        out = np.zeros(self.count)
+        _lib.check(_lib.load().adr_max_error(self._h, _dev_f64(x, self.n, "x"), _host_ptr(out)))
+        return out
 
     # -- learned initial guess (include/adr_cnn.h) --
     def features(self, first=0, count=None, out=None):

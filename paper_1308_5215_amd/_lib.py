@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libadr.so")
 
 # Names and numbering of include/adr.h
 OK, ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_STATE = 0, -1, -2, -3, -4
-MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE = 1, 2, 3, 4, 5
+MAXIT, BREAKDOWN_RHO, OMEGA_ZERO, ZERO_PIVOT, NONFINITE, INACCURATE = 1, 2, 3, 4, 5, 6
 UPWIND, CENTERED = 0, 1
 DIRICHLET, NEUMANN_XY = 0, 1
 FP64, FP32_FACTORS, FP32_SWEEPS = 0, 1, 2
@@ -21,6 +21,8 @@ EXPORTS = [
     "adr_set_sweep_rows", "adr_status_str", "adr_last_error", "adr_batch_assemble", "adr_batch_layout",
     "adr_batch_ilu0", "adr_batch_solve", "adr_autotune", "adr_use_stencil_tables", "adr_stencil_tables",
     "adr_last_call_ms", "adr_workspace_bytes", "adr_bind_workspace", "adr_set_sweep_ring", "adr_sweep_ring",
+    "adr_set_max_restarts", "adr_assemble_data", "adr_batch_assemble_data", "adr_max_error", "adr_classify",
+    "adr_stream_copy",
     # include/adr_cnn.h
     "adr_cnn_param_count", "adr_cnn_create", "adr_cnn_destroy", "adr_cnn_set_params", "adr_cnn_get_params",
     "adr_cnn_forward", "adr_cnn_gradient", "adr_cnn_adam", "adr_cnn_train_step", "adr_cnn_features",
@@ -31,7 +33,25 @@ EXPORTS = [
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("hist_len", ctypes.c_int32),
                 ("half_step", ctypes.c_int32), ("bnorm", ctypes.c_double),
-                ("true_relres", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+                ("true_relres", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("restarts", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ProblemData(ctypes.Structure):
+    """adr_problem_data: the caller's forcing and boundary data."""
+    _fields_ = [("f", ctypes.c_void_p), ("f_len", ctypes.c_int64),
+                ("u_x0", ctypes.c_void_p), ("u_x0_len", ctypes.c_int64),
+                ("u_xX", ctypes.c_void_p), ("u_xX_len", ctypes.c_int64),
+                ("u_y0", ctypes.c_void_p), ("u_y0_len", ctypes.c_int64),
+                ("u_yY", ctypes.c_void_p), ("u_yY_len", ctypes.c_int64),
+                ("f_on_device", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class InstanceClass(ctypes.Structure):
+    """adr_instance_class."""
+    _fields_ = [("pe_x", ctypes.c_double), ("pe_y", ctypes.c_double), ("g_y", ctypes.c_double),
+                ("neg_offdiag", ctypes.c_int64), ("nonneg_diag", ctypes.c_int64),
+                ("expect_fail", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -126,6 +146,20 @@ def load():
     L.adr_cnn_features.argtypes = [P, i32, i32, P]
     L.adr_batch_warm_start.restype = ctypes.c_int
     L.adr_batch_warm_start.argtypes = [P, P, P, I32P]
+    L.adr_set_max_restarts.restype = ctypes.c_int
+    L.adr_set_max_restarts.argtypes = [P, i32]
+    L.adr_assemble_data.restype = ctypes.c_int
+    L.adr_assemble_data.argtypes = [f64, f64, f64, i32, i32, i32, i32, ctypes.POINTER(ProblemData), P,
+                                    ctypes.POINTER(P)]
+    L.adr_batch_assemble_data.restype = ctypes.c_int
+    L.adr_batch_assemble_data.argtypes = [i32, D, D, D, I32P, I32P, I32P, I32P, ctypes.POINTER(ProblemData), P,
+                                          ctypes.POINTER(P)]
+    L.adr_max_error.restype = ctypes.c_int
+    L.adr_max_error.argtypes = [P, P, D]
+    L.adr_classify.restype = ctypes.c_int
+    L.adr_classify.argtypes = [f64, f64, f64, i32, i32, i32, i32, ctypes.POINTER(InstanceClass)]
+    L.adr_stream_copy.restype = ctypes.c_int
+    L.adr_stream_copy.argtypes = [P, P, i64, P]
     L.adr_status_str.restype = ctypes.c_char_p
     L.adr_status_str.argtypes = [i32]
     L.adr_last_error.restype = ctypes.c_char_p

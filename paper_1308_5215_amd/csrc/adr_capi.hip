@@ -150,6 +150,7 @@ struct adr_problem {
   double *lw = nullptr, *ls = nullptr, *invd = nullptr;
   float *lw32 = nullptr, *ls32 = nullptr, *invd32 = nullptr, *E32 = nullptr, *N32 = nullptr;
   int factored = 0, precision = 0;
+  int max_restarts = 8;        // true-residual confirmation (adr_set_max_restarts)
   // iteration vectors
   double *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
   double *ph = nullptr, *z = nullptr, *y = nullptr;
@@ -181,7 +182,7 @@ struct adr_problem {
   hipGraphExec_t gexec = nullptr;
   double *g_x = nullptr;
   double g_tol = -1;
-  int g_maxit = -1, g_prec = -1, g_rows = -1, g_K = 0, g_tab = -1, g_cmp = -1;
+  int g_maxit = -1, g_prec = -1, g_rows = -1, g_K = 0, g_tab = -1, g_cmp = -1, g_mr = -2;
 
   SweepSync sync() const { return SweepSync{ticket, handoff, err}; }
   Dia dia() const { return Dia{S, W, C, E, N}; }
@@ -348,6 +349,7 @@ IterBufs iter_bufs(adr_problem *P, double *x, double tol, int maxit) {
   B.hist = P->hist;
   B.tol = tol;
   B.maxit = maxit;
+  B.max_restarts = P->max_restarts;
   return B;
 }
 
@@ -402,8 +404,12 @@ adr_status set_rows(adr_problem *P, int R) {
   return build_table(P, R);
 }
 
-// Assemble instance k into its slices of the batched arrays.
-adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double amp) {
+// Value v[i] of an item of problem data with `len` entries (1: broadcast).
+inline double data_at(const double *v, int64_t len, int64_t i) { return v[len == 1 ? 0 : i]; }
+
+// Assemble instance k into its slices of the batched arrays.  d: the
+// caller's problem data (already validated), or NULL.
+adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double amp, const adr_problem_data *d) {
   const Inst &I = P->inst[k];
   const int nx = I.nx, ny = I.ny;
   const double eps = P->eps[k], X = P->X[k], Y = P->Y[k];
@@ -433,7 +439,21 @@ adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double a
     uxX[j] = (e1 * (1.0 - eyj[j])) * y;
     gxX[j] = (((-1.0 / X) * e1) * (1.0 - eyj[j])) * y;
   }
+  // the caller's boundary data replaces the manufactured values (for the
+  // Neumann sides it is the normal derivative)
+  const bool neu = P->bc[k] == ADR_BC_NEUMANN_XY;
+  if (d) {
+    for (int j = 0; j < ny; ++j) {
+      if (d->u_x0) ux0[j] = data_at(d->u_x0, d->u_x0_len, j);
+      if (d->u_xX) (neu ? gxX : uxX)[j] = data_at(d->u_xX, d->u_xX_len, j);
+    }
+    for (int i = 0; i < nx; ++i) {
+      if (d->u_y0) uy0[i] = data_at(d->u_y0, d->u_y0_len, i);
+      if (d->u_yY) (neu ? gyY : uyY)[i] = data_at(d->u_yY, d->u_yY_len, i);
+    }
+  }
   double *dtab = nullptr;
+  double *dfu = nullptr;      // host forcing array, uploaded
   size_t tb = 0;
   HIP_TRY(dalloc(&dtab, tx.size() + ty.size(), tb));
   hipError_t e = hipMemcpyAsync(dtab, tx.data(), tx.size() * sizeof(double), hipMemcpyHostToDevice, P->stream);
@@ -448,6 +468,25 @@ adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double a
   a.gxX = dy0 + 6 * ny;
   a.field = field_dev ? field_dev + I.off : nullptr;
   a.amp = amp;
+  a.fmode = 0;
+  a.fuser = nullptr;
+  a.fconst = 0.0;
+  if (d && d->f) {
+    if (d->f_len == 1 && !d->f_on_device) {
+      a.fmode = 2;
+      a.fconst = d->f[0];
+    } else if (d->f_on_device) {
+      a.fmode = 1;
+      a.fuser = d->f;
+    } else {
+      a.fmode = 1;
+      size_t fb = 0;
+      if (e == hipSuccess) e = dalloc(&dfu, (size_t)I.n, fb);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dfu, d->f, (size_t)I.n * sizeof(double), hipMemcpyHostToDevice, P->stream);
+      a.fuser = dfu;
+    }
+  }
   a.S = P->S + I.off; a.W = P->W + I.off; a.C = P->C + I.off; a.E = P->E + I.off; a.N = P->N + I.off;
   a.rhs = P->rhs + I.off;
   a.F = P->F + I.off;
@@ -456,6 +495,7 @@ adr_status assemble_one(adr_problem *P, int k, const double *field_dev, double a
   if (e == hipSuccess) e = launch_assemble(a, make_geom(I.n), P->stream);
   hipError_t es = hipStreamSynchronize(P->stream);
   (void)hipFree(dtab);
+  if (dfu) (void)hipFree(dfu);
   HIP_TRY(e);
   HIP_TRY(es);
   return ADR_OK;
@@ -519,6 +559,7 @@ const char *adr_status_str(int32_t st) {
     case ADR_OMEGA_ZERO: return "omega = 0";
     case ADR_ZERO_PIVOT: return "zero or non-finite pivot";
     case ADR_NONFINITE: return "non-finite value";
+    case ADR_INACCURATE: return "true residual above tolerance after the allowed restarts";
     default: return "unknown status";
   }
 }
@@ -551,11 +592,36 @@ void adr_destroy(adr_problem *P) {
   delete P;
 }
 
-adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X, const double *Y,
-                              const int32_t *nx, const int32_t *ny, const int32_t *scheme,
-                              const int32_t *bc, const double *field_dev, double amp, void *stream,
-                              adr_problem **out) {
-  g_last_error.clear();
+}  // extern "C"
+
+namespace {
+
+adr_status check_data(int k, int nx, int ny, const adr_problem_data &d) {
+  struct Item {
+    const char *name;
+    const double *p;
+    int64_t len, full;
+  } items[] = {{"f", d.f, d.f_len, (int64_t)nx * ny}, {"u_x0", d.u_x0, d.u_x0_len, ny},
+               {"u_xX", d.u_xX, d.u_xX_len, ny}, {"u_y0", d.u_y0, d.u_y0_len, nx},
+               {"u_yY", d.u_yY, d.u_yY_len, nx}};
+  for (const Item &it : items) {
+    if (!it.p) {
+      if (it.len != 0) return fail(ADR_ERR_ARG, "instance %d: %s is NULL but has length %lld", k, it.name, (long long)it.len);
+      continue;
+    }
+    if (it.len != 1 && it.len != it.full)
+      return fail(ADR_ERR_ARG, "instance %d: %s has %lld values; expected 1 or %lld", k, it.name, (long long)it.len,
+                  (long long)it.full);
+  }
+  if (d.f_on_device && d.f && d.f_len != (int64_t)nx * ny)
+    return fail(ADR_ERR_ARG, "instance %d: a device forcing array needs nx*ny = %lld values", k, (long long)nx * ny);
+  if (d.f_on_device != 0 && d.f_on_device != 1) return fail(ADR_ERR_ARG, "instance %d: f_on_device must be 0 or 1", k);
+  return ADR_OK;
+}
+
+adr_status batch_assemble(int32_t count, const double *eps, const double *X, const double *Y, const int32_t *nx,
+                          const int32_t *ny, const int32_t *scheme, const int32_t *bc, const double *field_dev,
+                          double amp, const adr_problem_data *data, void *stream, adr_problem **out) {
   if (!out) return fail(ADR_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (count < 1) return fail(ADR_ERR_ARG, "count must be >= 1 (got %d)", count);
@@ -575,6 +641,11 @@ adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X,
       return fail(ADR_ERR_ARG, "instance %d: nx*ny must be < 2^31", k);
   }
   if (field_dev && !std::isfinite(amp)) return fail(ADR_ERR_ARG, "amp must be finite");
+  if (data)
+    for (int k = 0; k < count; ++k) {
+      adr_status dst = check_data(k, nx[k], ny[k], data[k]);
+      if (dst != ADR_OK) return dst;
+    }
 
   adr_problem *P = new adr_problem();
   auto bail = [&](adr_status st) {
@@ -605,13 +676,39 @@ adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X,
       dalloc(&P->scal, 8, P->bytes) != hipSuccess || dalloc(&P->bad, (size_t)count, P->bytes) != hipSuccess)
     return bail(fail(ADR_ERR_NOMEM, "device allocation failed"));
   for (int k = 0; k < count; ++k) {
-    st = assemble_one(P, k, field_dev, amp);
+    st = assemble_one(P, k, data ? nullptr : field_dev, amp, data ? &data[k] : nullptr);
     if (st != ADR_OK) return bail(st);
   }
   st = refresh_stencil_tables(P);
   if (st != ADR_OK) return bail(st);
   *out = P;
   return ADR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+adr_status adr_batch_assemble(int32_t count, const double *eps, const double *X, const double *Y,
+                              const int32_t *nx, const int32_t *ny, const int32_t *scheme,
+                              const int32_t *bc, const double *field_dev, double amp, void *stream,
+                              adr_problem **out) {
+  g_last_error.clear();
+  return batch_assemble(count, eps, X, Y, nx, ny, scheme, bc, field_dev, amp, nullptr, stream, out);
+}
+
+adr_status adr_batch_assemble_data(int32_t count, const double *eps, const double *X, const double *Y,
+                                   const int32_t *nx, const int32_t *ny, const int32_t *scheme,
+                                   const int32_t *bc, const adr_problem_data *data, void *stream,
+                                   adr_problem **out) {
+  g_last_error.clear();
+  return batch_assemble(count, eps, X, Y, nx, ny, scheme, bc, nullptr, 0.0, data, stream, out);
+}
+
+adr_status adr_assemble_data(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme, int32_t bc,
+                             const adr_problem_data *data, void *stream, adr_problem **out) {
+  g_last_error.clear();
+  return batch_assemble(1, &eps, &X, &Y, &nx, &ny, &scheme, &bc, nullptr, 0.0, data, stream, out);
 }
 
 adr_status adr_assemble(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme,
@@ -926,7 +1023,7 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
   if (K > maxit && maxit > 0) K = maxit;
   if (!P->gexec || P->g_x != x || P->g_tol != tol || P->g_maxit != maxit || P->g_prec != P->precision ||
       P->g_rows != P->rows || P->g_K != K || P->g_tab != (P->stencil_tab() != nullptr) ||
-      P->g_cmp != P->ring_compact()) {
+      P->g_cmp != P->ring_compact() || P->g_mr != P->max_restarts) {
     st = build_graph(P, B, K);
     if (st != ADR_OK) return st;
     P->g_x = x;
@@ -936,6 +1033,7 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
     P->g_rows = P->rows;
     P->g_cmp = P->ring_compact();
     P->g_tab = P->stencil_tab() != nullptr;
+    P->g_mr = P->max_restarts;
   }
   auto all_done = [&]() {
     for (int k = 0; k < P->count; ++k)
@@ -999,6 +1097,7 @@ adr_status adr_batch_solve(adr_problem *P, double tol, int32_t maxit, const doub
       info[k].bnorm = S.bnorm;
       info[k].true_relres = S.bnorm > 0.0 ? std::sqrt(S.true_res2) / S.bnorm : 0.0;
       info[k].solve_ms = ms;
+      info[k].restarts = S.restarts;
     }
     if (result == ADR_OK && S.status != ADR_OK) result = (adr_status)S.status;
   }
@@ -1071,6 +1170,119 @@ adr_status adr_batch_warm_start(adr_problem *P, adr_cnn *net, double *x, int32_t
     if (used) used[k] = keep ? 1 : 0;
   }
   HIP_TRY(hipStreamSynchronize(P->stream));
+  return ADR_OK;
+}
+
+adr_status adr_set_max_restarts(adr_problem *P, int32_t n) {
+  g_last_error.clear();
+  if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
+  if (n < -1) return fail(ADR_ERR_ARG, "max_restarts must be >= -1 (got %d)", n);
+  P->max_restarts = n;
+  return ADR_OK;
+}
+
+adr_status adr_max_error(adr_problem *P, const double *x, double *err_host) {
+  g_last_error.clear();
+  if (!P || !x || !err_host) return fail(ADR_ERR_ARG, "NULL argument");
+  double *res = P->scal + 1;   // device scalar (scal[0] is the assembly's max|f|)
+  for (int k = 0; k < P->count; ++k) {
+    const Inst &I = P->inst[k];
+    MaxErrArgs a;
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.bc = P->bc[k];
+    a.X = P->X[k];
+    a.Y = P->Y[k];
+    a.dx = P->X[k] / (double)(I.nx + 1);
+    a.dy = P->Y[k] / (double)(I.ny + 1);
+    a.x = x + I.off;
+    a.partials = P->partials;
+    a.out = res;
+    const int64_t nodes = (int64_t)(I.nx + 2) * (I.ny + 2);
+    if (nodes > 0x7fffffff) return fail(ADR_ERR_ARG, "instance %d: grid too large for adr_max_error", k);
+    HIP_TRY(launch_max_error(a, make_geom(nodes), P->stream));
+    HIP_TRY(hipMemcpyAsync(err_host + k, res, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+  }
+  return ADR_OK;
+}
+
+adr_status adr_classify(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme, int32_t bc,
+                        adr_instance_class *out) {
+  g_last_error.clear();
+  if (!out) return fail(ADR_ERR_ARG, "out is NULL");
+  memset(out, 0, sizeof(*out));
+  if (!(eps > 0.0) || !(X > 0.0) || !(Y > 0.0) || !std::isfinite(eps) || !std::isfinite(X) || !std::isfinite(Y))
+    return fail(ADR_ERR_ARG, "eps, X and Y must be finite and > 0");
+  if (nx < 1 || ny < 1) return fail(ADR_ERR_ARG, "nx and ny must be >= 1 (got %d, %d)", nx, ny);
+  if (scheme != ADR_UPWIND && scheme != ADR_CENTERED) return fail(ADR_ERR_ARG, "unknown scheme %d", scheme);
+  if (bc != ADR_BC_DIRICHLET && bc != ADR_BC_NEUMANN_XY) return fail(ADR_ERR_ARG, "unknown bc %d", bc);
+  // the Section 4 coefficients, per column (through a) and per row (through
+  // b), evaluated as the assembly kernel evaluates them
+  const double dx = X / (double)(nx + 1), dy = Y / (double)(ny + 1);
+  const double dx2 = dx * dx, dy2 = dy * dy;
+  const double cx = eps * dy2, cy = eps * dx2, gx = dx * dy2, gy = dx2 * dy;
+  std::vector<double> ax((size_t)nx), by((size_t)ny);
+  double amax = 0.0, bmax = 0.0;
+  for (int i = 0; i < nx; ++i) {
+    const double x = (double)(i + 1) * dx;
+    ax[i] = 1.0 + x * x;
+    amax = std::max(amax, ax[i]);
+  }
+  for (int j = 0; j < ny; ++j) {
+    by[j] = X * std::exp(-(double)(j + 1) * dy);
+    bmax = std::max(bmax, by[j]);
+  }
+  out->pe_x = amax * dx / eps;
+  out->pe_y = bmax * dy / eps;
+  out->g_y = X * (1.0 - std::exp(-Y)) / eps;
+  // negative couplings: W and E vary with the column only, S and N with the
+  // row only; boundary couplings are absent (i = 0 has no W, ...)
+  int64_t negw = 0, nege = 0, negs = 0, negn = 0;
+  for (int i = 0; i < nx; ++i) {
+    const double w = scheme == ADR_UPWIND ? cx - ax[i] * gx : cx - 0.5 * (ax[i] * gx);
+    const double e = scheme == ADR_UPWIND ? cx : cx + 0.5 * (ax[i] * gx);
+    negw += (i > 0 && w < 0.0);
+    nege += (i < nx - 1 && e < 0.0);
+  }
+  for (int j = 0; j < ny; ++j) {
+    const double sj = scheme == ADR_UPWIND ? cy - by[j] * gy : cy - 0.5 * (by[j] * gy);
+    const double nj = scheme == ADR_UPWIND ? cy : cy + 0.5 * (by[j] * gy);
+    negs += (j > 0 && sj < 0.0);
+    negn += (j < ny - 1 && nj < 0.0);
+  }
+  out->neg_offdiag = (negw + nege) * ny + (negs + negn) * nx;
+  // diagonal sign, point by point (the Neumann closure adds E, N on the
+  // outer sides)
+  int64_t nonneg = 0;
+  for (int j = 0; j < ny; ++j) {
+    const double nj = scheme == ADR_UPWIND ? cy : cy + 0.5 * (by[j] * gy);
+    for (int i = 0; i < nx; ++i) {
+      double c = scheme == ADR_UPWIND ? (ax[i] * gx + by[j] * gy) - 2.0 * (cx + cy) : -2.0 * (cx + cy);
+      if (bc == ADR_BC_NEUMANN_XY) {
+        if (i == nx - 1) c = c + (scheme == ADR_UPWIND ? cx : cx + 0.5 * (ax[i] * gx));
+        if (j == ny - 1) c = c + nj;
+      }
+      nonneg += (c >= 0.0);
+    }
+  }
+  out->nonneg_diag = nonneg;
+  out->expect_fail = ((bc == ADR_BC_NEUMANN_XY && out->g_y > 20.0) || nonneg > 0) ? 1 : 0;
+  return ADR_OK;
+}
+
+adr_status adr_stream_copy(const double *src, double *dst, int64_t n, void *stream) {
+  g_last_error.clear();
+  if (!src || !dst || n < 0) return fail(ADR_ERR_ARG, "bad argument");
+  if (n == 0) return ADR_OK;
+  int dev = 0, cus = 256;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t want = (n / 2 + 4 * 256 - 1) / (4 * 256);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 16));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_stream_copy(src, dst, n, blocks, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return ADR_OK;
 }
 

@@ -72,8 +72,9 @@ __device__ __forceinline__ double wave_reduce_max(double v) {
 }
 
 // Reduce NS dd values and one max over a block of NT threads; thread 0
-// writes them to partials[slot * nblk + block].
-template <int NS, bool MAX, int NT = BLK>
+// writes them to partials[(SLOT0 + q) * nblk + block] (q < NS) and the max
+// to slot 3.
+template <int NS, bool MAX, int NT = BLK, int SLOT0 = 0>
 __device__ __forceinline__ void block_partials(const dd (&v)[NS > 0 ? NS : 1], double mx,
                                                double2 *partials, int nblk, int bid) {
   __shared__ dd sh[NS > 0 ? NS : 1][NT / 64];
@@ -95,7 +96,7 @@ __device__ __forceinline__ void block_partials(const dd (&v)[NS > 0 ? NS : 1], d
       dd r = sh[q][0];
 #pragma unroll
       for (int u = 1; u < NT / 64; ++u) r = dd_add(r, sh[q][u]);
-      partials[(size_t)q * nblk + bid] = make_double2(r.hi, r.lo);
+      partials[(size_t)(SLOT0 + q) * nblk + bid] = make_double2(r.hi, r.lo);
     }
     if (MAX) {
       double m = shm[0];

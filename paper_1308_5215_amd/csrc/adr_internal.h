@@ -18,9 +18,12 @@ namespace adr {
 
 // Device-resident scalar state of one BiCGSTAB solve.  Written only by the
 // single-block finalize kernels (and the init kernel), read by every kernel
-// of the iteration; kernels that find phase != RUNNING return at once, so
+// of the iteration; kernels that find phase DONE return at once, so
 // iterations launched after the stop are no-ops and the pass count is exact.
-enum Phase : int32_t { RUNNING = 0, HALF_STEP = 1, DONE = 2 };
+// CHECK: the recursively updated residual passed the stopping test; the next
+// pass slot computes the true residual b - A x (written to r, r^ and p as the
+// start of a restart) and its finalize step accepts the solve or restarts it.
+enum Phase : int32_t { RUNNING = 0, HALF_STEP = 1, DONE = 2, CHECK = 3 };
 
 struct SolveState {
   double rho, rho_prev, alpha, omega, beta;
@@ -32,6 +35,8 @@ struct SolveState {
   int32_t half_step;  // 1 if ended on the ||s|| test
   int32_t maxit;
   int32_t zero_x;     // b == 0: x must be cleared
+  int32_t restarts;   // restarts from the current iterate so far
+  int32_t max_restarts;   // < 0: accept the recursive residual's test alone
   int32_t pad;
 };
 
@@ -108,6 +113,9 @@ struct AssembleArgs {
   const double *yj, *bj, *eyj, *ebj, *ux0, *uxX, *gxX;
   const double *field;  // optional
   double amp;
+  int fmode;            // 0: manufactured f (+ field); 1: f = fuser[k]; 2: f = fconst
+  const double *fuser;  // device, fmode 1
+  double fconst;        // fmode 2
   double *S, *W, *C, *E, *N, *rhs;
   double *F;           // optional: the forcing f at every unknown
   double2 *partials;   // workspace for the max|f| reduction
@@ -131,6 +139,7 @@ struct IterBufs {
   double *hist;        // [ninst][2][maxit + 1]
   double tol;
   int maxit;
+  int max_restarts;    // see SolveState::max_restarts
 };
 hipError_t launch_init(const IterBufs &B, const BatchGeom &g, hipStream_t s);
 hipError_t launch_pass_p(const IterBufs &B, const BatchGeom &g, hipStream_t s);
@@ -139,6 +148,20 @@ hipError_t launch_pass_s(const IterBufs &B, const BatchGeom &g, hipStream_t s);
 hipError_t launch_pass_t(const IterBufs &B, const BatchGeom &g, hipStream_t s);
 hipError_t launch_pass_xr(const IterBufs &B, const BatchGeom &g, hipStream_t s);
 hipError_t launch_true_residual(const IterBufs &B, const BatchGeom &g, hipStream_t s);
+
+// max |U - u_exact| over the (nx+2) x (ny+2) nodes of one instance, U being
+// the solution x with the boundary values (Dirichlet: exact u; Neumann edges
+// reconstructed from the one-sided closure), into *out (device).
+struct MaxErrArgs {
+  int nx, ny, bc;
+  double X, Y, dx, dy;
+  const double *x;
+  double2 *partials;
+  double *out;
+};
+hipError_t launch_max_error(const MaxErrArgs &a, const Stream1D &g, hipStream_t s);
+// dst[k] = src[k], k < n: a plain streaming copy (bandwidth reference).
+hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, int blocks, hipStream_t s);
 
 // Wavefront kernels.  rows = strip height R (15 or 31).
 struct Factors64 {

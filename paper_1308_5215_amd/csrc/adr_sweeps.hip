@@ -226,7 +226,9 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   __syncthreads();
   const int strip = s_strip;
   const Inst I = p.g.inst[s_inst];
-  if (p.st && p.st[s_inst].phase != RUNNING) {   // this instance has stopped
+  // RUNNING: a pass; CHECK: the first pass of a possible restart (M^{-1} of
+  // the true residual); any other phase: this instance has stopped
+  if (p.st && p.st[s_inst].phase != RUNNING && p.st[s_inst].phase != CHECK) {
     strip_finish(p.sync, p.g.nstrips);
     return;
   }
