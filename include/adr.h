@@ -336,6 +336,23 @@ adr_status adr_dot(const double *x_dev, const double *y_dev, int64_t n, void *st
  * the roofline figures.  Synchronous on return. */
 adr_status adr_stream_copy(const double *src_dev, double *dst_dev, int64_t n, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * adr_dot_noalloc -- adr_dot for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  The same double-double inner product and the same result
+ * bits, but its per-block partial sums live in a fixed library-owned device
+ * array (2048 entries of 16 bytes, 32 KiB, on each GPU the library runs on,
+ * held until the process ends) instead of memory allocated per call, and the
+ * result goes to device memory.  No hipMalloc or hipFree is made.
+ * x_dev, y_dev: n doubles each; out_dev: one double of device memory.
+ * 0 <= n <= 2^31 - 1 (at most 2048 partial sums), else ADR_ERR_ARG.
+ * Asynchronous: queued on `stream`, the result is in out_dev when the stream
+ * reaches it.  Calls on one GPU share the array: calls that overlap (other
+ * streams, other host threads) race on it and must be serialised.
+ * ------------------------------------------------------------------------- */
+adr_status adr_dot_noalloc(const double *x_dev, const double *y_dev, int64_t n, void *stream,
+                           double *out_dev);
+
 /* Bytes of device memory the problem holds (after ilu0 / solve buffers). */
 size_t adr_device_bytes(const adr_problem *p);
 

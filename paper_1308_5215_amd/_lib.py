@@ -22,7 +22,7 @@ EXPORTS = [
     "adr_batch_ilu0", "adr_batch_solve", "adr_autotune", "adr_use_stencil_tables", "adr_stencil_tables",
     "adr_last_call_ms", "adr_workspace_bytes", "adr_bind_workspace", "adr_set_sweep_ring", "adr_sweep_ring",
     "adr_set_max_restarts", "adr_assemble_data", "adr_batch_assemble_data", "adr_max_error", "adr_classify",
-    "adr_stream_copy",
+    "adr_stream_copy", "adr_dot_noalloc",
     # include/adr_cnn.h
     "adr_cnn_param_count", "adr_cnn_create", "adr_cnn_destroy", "adr_cnn_set_params", "adr_cnn_get_params",
     "adr_cnn_forward", "adr_cnn_gradient", "adr_cnn_adam", "adr_cnn_train_step", "adr_cnn_features",
@@ -160,6 +160,8 @@ def load():
     L.adr_classify.argtypes = [f64, f64, f64, i32, i32, i32, i32, ctypes.POINTER(InstanceClass)]
     L.adr_stream_copy.restype = ctypes.c_int
     L.adr_stream_copy.argtypes = [P, P, i64, P]
+    L.adr_dot_noalloc.restype = ctypes.c_int
+    L.adr_dot_noalloc.argtypes = [P, P, i64, P, P]
     L.adr_status_str.restype = ctypes.c_char_p
     L.adr_status_str.argtypes = [i32]
     L.adr_last_error.restype = ctypes.c_char_p

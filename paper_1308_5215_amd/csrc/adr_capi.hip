@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -102,6 +103,18 @@ template <class T>
 hipError_t palloc(adr_problem *P, T **p, size_t count);
 template <class T>
 void pfree(adr_problem *P, T *&p);
+
+// Partial sums of adr_dot_noalloc: one 16-byte entry per streaming block of
+// the inner product (at most 2048 blocks for n < 2^31, see stream_geom), in a
+// fixed device array instead of per-call allocations.  Host code never uses
+// the symbol itself as an address: dot_scratch() looks up this device's copy
+// with hipGetSymbolAddress once and keeps the pointer per device.
+constexpr int DOT_SCRATCH_BLOCKS = 2048;
+static __device__ __align__(256) double2 scratch[DOT_SCRATCH_BLOCKS];
+
+std::mutex g_scratch_mu;
+constexpr int MAX_DEVICES = 64;
+double2 *g_scratch[MAX_DEVICES] = {};
 
 // Strip height used until the autotuner or the caller picks one: 31 rows
 // (measured faster than 15 for every square grid from 128^2 to 4096^2: half
@@ -1283,6 +1296,51 @@ adr_status adr_stream_copy(const double *src, double *dst, int64_t n, void *stre
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_stream_copy(src, dst, n, blocks, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return ADR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// This device's copy of the adr_dot_noalloc partial-sum array (looked up
+// once per device, with that device current).
+adr_status dot_scratch(double2 **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(ADR_ERR_DEVICE, "device %d beyond the %d supported", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ADR_ERR_DEVICE, "no device address for the inner-product scratch array");
+    g_scratch[dev] = (double2 *)p;
+  }
+  *out = g_scratch[dev];
+  return ADR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+adr_status adr_dot_noalloc(const double *x, const double *y, int64_t n, void *stream, double *out_dev) {
+  g_last_error.clear();
+  if (!x || !y || !out_dev) return fail(ADR_ERR_ARG, "NULL argument");
+  if (n < 0 || n > 0x7fffffff) return fail(ADR_ERR_ARG, "n must be in [0, 2^31 - 1] (got %lld)", (long long)n);
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) {
+    HIP_TRY(launch_fill(out_dev, 1, 0.0, s));
+    return ADR_OK;
+  }
+  const Stream1D g = make_geom(n);
+  if (g.nblk > DOT_SCRATCH_BLOCKS)
+    return fail(ADR_ERR_ARG, "n = %lld needs %d partial sums; the array holds %d", (long long)n, g.nblk,
+                DOT_SCRATCH_BLOCKS);
+  double2 *part = nullptr;
+  adr_status st = dot_scratch(&part);
+  if (st != ADR_OK) return st;
+  HIP_TRY(launch_dot(x, y, g, part, out_dev, s));
   return ADR_OK;
 }
 
