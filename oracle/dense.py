@@ -2,15 +2,17 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-* ``dense_matrix``: the five diagonals as a dense array (the appendix builds A
-  dense, ``zeros(dime,dime)``, with the same lexicographic ordering).
+* ``dense_matrix``: the five diagonals as a dense array, in the paper's
+  lexicographic ordering.
 * ``exact_discrete``: the exact solution of the discrete system by LU with
   partial pivoting (numpy/LAPACK), for the error tables of Section 6.
-* ``truncated_lu``: the appendix's "ILUdecomposition2" routine -- full Gaussian
-  elimination with fill, then every entry outside A's pattern set to zero --
-  which the printed iteration counts of Section 6 were produced with.
-* ``split_lu``: the instructor's splitting ("ILUdecomposition"): L = unit
-  lower part of A, U = upper part of A (Section 6.4-6.5 comparisons).
+* ``truncated_lu``: the preconditioner under which the printed iteration
+  counts of Section 6 come out -- the complete LU factors of A (no pivoting,
+  fill kept during the elimination) with every entry outside A's pattern
+  dropped afterwards, i.e. not the ILU(0) of Section 5.1, whose elimination
+  drops the fill as it goes.
+* ``split_lu``: the splitting preconditioner of the Section 6.4-6.5
+  comparisons: L = unit lower part of A, U = upper part of A.
 * ``identity``: M = I, the unpreconditioned BiCGSTAB of Section 6.5 / 6.8.
 """
 import numpy as np
@@ -46,21 +48,29 @@ def _five_point_factors(P, Lo, Up):
     return core.Factors(lw, ls, invd, ue, un)
 
 
+def lu_no_pivoting(A):
+    """Complete LU factors of A without pivoting, A = L U with L unit lower,
+    in the right-looking (outer-product) form of Golub & Van Loan, Matrix
+    Computations, Algorithm 3.2.1: column k of L is column k of the current
+    Schur complement over its pivot, which is then updated by a rank-one
+    product."""
+    S = np.array(A, dtype=np.float64)
+    n = S.shape[0]
+    L = np.eye(n)
+    for k in range(n - 1):
+        L[k + 1:, k] = S[k + 1:, k] / S[k, k]
+        S[k + 1:, k + 1:] -= np.outer(L[k + 1:, k], S[k, k + 1:])
+        S[k + 1:, k] = 0.0
+    return L, np.triu(S)
+
+
 def truncated_lu(P):
-    """Full LU without pivoting (with fill), then truncation to A's pattern."""
-    A0 = dense_matrix(P)
-    A = A0.copy()
-    n = A.shape[0]
-    for kk in range(n - 1):
-        rows = np.nonzero(A[kk + 1:, kk])[0] + kk + 1
-        for i in rows:
-            lam = A[i, kk] / A[kk, kk]
-            A[i, kk + 1:] -= lam * A[kk, kk + 1:]
-            A[i, kk] = lam
-    A[A0 == 0] = 0.0
-    Lo = np.tril(A, -1) + np.eye(n)
-    Up = np.triu(A)
-    return _five_point_factors(P, Lo, Up)
+    """The complete factors (``lu_no_pivoting``) restricted to A's pattern."""
+    A = dense_matrix(P)
+    L, U = lu_no_pivoting(A)
+    keep = A != 0
+    np.fill_diagonal(keep, True)
+    return _five_point_factors(P, np.where(keep, L, 0.0), np.where(keep, U, 0.0))
 
 
 def split_lu(P):

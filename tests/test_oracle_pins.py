@@ -356,6 +356,21 @@ def test_bicgstab_reaches_the_dense_lu_solution(orc, nx, ny, scheme, bc, eps):
     assert s.hist_l2[-1] < 1e-14 * s.bnorm
 
 
+def test_complete_lu_reproduces_a_and_scipy():
+    """The complete factors behind the truncated preconditioner: L U = A, and
+    the same factors as SciPy's LU of a matrix that needs no row exchange
+    (diagonally dominant, so partial pivoting keeps the natural order)."""
+    import scipy.linalg
+    P = core.assemble(2.0, 1.0, 1.0, 7, 5, core.CENTERED, core.DIRICHLET)
+    A = dense.dense_matrix(P)
+    L, U = dense.lu_no_pivoting(A)
+    assert np.abs(L @ U - A).max() <= 1e-14 * np.abs(A).max()
+    perm, L2, U2 = scipy.linalg.lu(A)
+    assert np.array_equal(perm, np.eye(P.n))
+    np.testing.assert_allclose(L, L2, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(U, U2, rtol=1e-12, atol=1e-15 * np.abs(A).max())
+
+
 def test_table_6_2_iterations_with_the_appendix_settings(orc, tables):
     """The appendix's solver settings (truncated full LU, x0 = 10, absolute
     1e-20 test) reproduce the Section 6.2 iteration counts: the upwind row
