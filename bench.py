@@ -33,10 +33,13 @@ PEAK_HBM_GBS = 8000.0
 
 
 def kernel_bytes(precision="fp64", tables=True):
-    """Algorithmic bytes per unknown of each kernel: what it must move with
-    perfect reuse of neighbours.  With stencil tables the iteration reads S,
-    W, E, N from per-column / per-row tables (a few KB) instead of four full
-    diagonals; "dia" gives the figures of the plain five-diagonal reads."""
+    """Bytes per unknown of each kernel with perfect reuse of neighbours.
+    tables=False: the algorithmic bytes of the five-diagonal method (L sweep
+    q, lw, ls in, y out: 32; U sweep y, E, N, invd in, z out: 40; stencil
+    product with its dot 64; a pass 392 in FP64) -- the figures the roofline
+    is priced on.  tables=True: what the kernels actually read, S, W, E, N
+    coming from per-column / per-row tables of a few KB (24, 24, 32; a pass
+    280)."""
     f = 4 if precision == "fp32_factors" else 8          # bytes of a stored factor
     if tables:
         ls = 8 + 8 + 8 if precision == "fp64" else 8 + 2 * f + 8   # q, invd (FP64) | q, lw, ls; y out
@@ -65,6 +68,7 @@ def parse():
     ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--maxit", type=int, default=20000)
+    ap.add_argument("--variant-maxit", type=int, default=14000, help="pass limit of the mixed-precision variants")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--rows", type=int, default=0, help="sweep strip height (0 = automatic)")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -206,6 +210,20 @@ def run_batch(args):
     st = np.asarray(res.status)
     its = np.asarray(res.iters)
     counts = {int(k): int((st == k).sum()) for k in np.unique(st)}
+    # the instance classifier's expectation against the outcome
+    expect = np.array([adr.classify(d["eps"], d["X"], d["Y"], d["n"], d["n"], d["scheme"], d["bc"], args.tol).expect_fail
+                       for d in inst])
+    failed = st != adr.OK
+    confusion = {"expected_fail_failed": int((expect & failed).sum()),
+                 "expected_fail_converged": int((expect & ~failed).sum()),
+                 "expected_ok_failed": int((~expect & failed).sum()),
+                 "expected_ok_converged": int((~expect & ~failed).sum())}
+    log("  classifier vs outcome: %s" % confusion)
+    per_instance = [dict(k=k, n=d["n"], eps=round(d["eps"], 6), X=round(d["X"], 4), Y=round(d["Y"], 4),
+                         scheme=d["scheme"], bc=d["bc"], status=int(st[k]), iters=int(its[k]),
+                         restarts=int(res.restarts[k]), expect_fail=bool(expect[k]))
+                    for k, d in enumerate(inst)]
+    tr_ok = np.asarray(res.true_relres)[~failed]
     work = float(sum(N[k] * its[k] for k in range(len(inst))))
     batch_s = float(np.mean(times)) / 1e3
     xb = [v.clone() for v in b.split(res.x)]
@@ -264,6 +282,9 @@ def run_batch(args):
                    "precision": args.batch_precision, "tol": args.tol, "maxit": args.batch_maxit,
                    "total_unknowns": int(sum(N)), "seed": 1308},
         "statuses": counts,
+        "classifier_vs_outcome": confusion,
+        "restarts_total": int(np.sum(res.restarts)),
+        "true_relres_max_of_ok": float(tr_ok.max()) if tr_ok.size else None,
         "unknown_passes_per_s": round(work / batch_s, 1),
         "hbm_gbs_algorithmic": round(kernel_bytes(args.batch_precision)["iteration"] * work / batch_s / 1e9, 1),
         "sequential": {"solve_s": round(seq_s, 3), "instances_timed": len(sample),
@@ -274,6 +295,9 @@ def run_batch(args):
         "sweep_ring": "compact" if rows[1] else "deep",
         "cpu_baseline": cpu,
     }
+    with open(os.path.join(ROOT, "gpurun_out", "batch_instances.json") if os.path.isdir(
+            os.path.join(ROOT, "gpurun_out")) else os.devnull, "w") as fh:
+        json.dump(per_instance, fh)
     print(json.dumps(out), flush=True)
 
 
@@ -384,12 +408,17 @@ def run_large(args):
             continue
         res = prob.solve(tol=args.tol, maxit=args.large_maxit)
         ms_it = res.solve_ms / max(res.iters, 1)
-        solves[sc] = dict(status=int(res.status), iters=int(res.iters), solve_s=round(res.solve_ms / 1e3, 3),
+        c = adr.classify(eps, X, Y, n, n, sc, "dirichlet")
+        solves[sc] = dict(status=int(res.status), iters=int(res.iters), restarts=int(res.restarts),
+                          solve_s=round(res.solve_ms / 1e3, 3),
                           ms_per_iter=round(ms_it, 3), true_relres=res.true_relres,
+                          max_error=prob.max_error(res.x),
                           last_relres=float(res.hist_l2[-1] / res.bnorm) if res.bnorm > 0 else None,
-                          algorithmic_gbs=round(bytes_pass["fp32_factors"] * N / (ms_it * 1e-3) / 1e9, 1))
-        log("  dirichlet %s: status %d passes %d %.2f s (%.2f ms/pass)" % (sc, res.status, res.iters,
-                                                                         res.solve_ms / 1e3, ms_it))
+                          algorithmic_gbs=round(bytes_pass["fp32_factors"] * N / (ms_it * 1e-3) / 1e9, 1),
+                          pe_x=round(c.pe_x, 3), neg_offdiag=int(c.neg_offdiag), expected_to_fail=c.expect_fail)
+        log("  dirichlet %s: status %d passes %d restarts %d %.2f s (%.2f ms/pass) true relres %.2e max error %.3e" %
+            (sc, res.status, res.iters, res.restarts, res.solve_ms / 1e3, ms_it, res.true_relres,
+             solves[sc]["max_error"]))
         del prob, res
         prob = adr.assemble(eps, X, Y, n, n, sc, "neumann")
         try:
@@ -402,6 +431,7 @@ def run_large(args):
         res = prob.solve(tol=args.tol, maxit=args.neumann_window)
         ms_it = res.solve_ms / max(res.iters, 1)
         windows[sc] = dict(status=int(res.status), iters=int(res.iters), solve_ms=round(res.solve_ms, 2),
+                           restarts=int(res.restarts), true_relres=res.true_relres,
                            algorithmic_gbs=round(bytes_pass["fp32_factors"] * N / (ms_it * 1e-3) / 1e9, 1),
                            last_relres=float(res.hist_l2[-1] / res.bnorm) if res.bnorm > 0 else None)
         log("  neumann %s: status %d after %d passes" % (sc, res.status, res.iters))
@@ -478,6 +508,37 @@ def run_kernels(args):
                       "precision": args.precision}), flush=True)
 
 
+def copy_reference_gbs(dev, reps=5):
+    """Bandwidth of the library's plain streaming copy kernel (1 GiB read and
+    1 GiB written), timed with events on the current stream: the practical
+    HBM ceiling beside the 8 TB/s peak."""
+    import torch
+    import paper_1308_5215_amd as adr
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    adr.stream_copy(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        adr.stream_copy(a, b)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
+def solve_record(prob, res, extra=None):
+    """Status, passes, restarts, true relative residual and discretisation
+    error (max |U - u_exact| over the grid, adr_max_error) of one solve."""
+    d = dict(status=int(res.status), iters=int(res.iters), restarts=int(res.restarts),
+             solve_s=round(res.solve_ms / 1e3, 4), true_relres=float(res.true_relres),
+             max_error=prob.max_error(res.x))
+    if extra:
+        d.update(extra)
+    return d
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -501,15 +562,14 @@ def main():
     torch.cuda.set_device(dev)
     n = args.n
     N = n * n
-    stream = torch.cuda.current_stream()
     schemes = ("upwind", "centered")
     tables_used = []
 
-    def hot_path(scheme, bc="dirichlet", maxit=args.maxit):
+    def hot_path(scheme, bc="dirichlet", maxit=args.maxit, precision=args.precision):
         prob = adr.assemble(args.eps, 1.0, 1.0, n, n, scheme, bc)
         if args.rows:
             prob.set_sweep_rows(args.rows)
-        prob.ilu0(args.precision)
+        prob.ilu0(precision)
         res = prob.solve(tol=args.tol, maxit=maxit)
         tables_used.append(prob.stencil_tables)
         return prob, res
@@ -526,13 +586,17 @@ def main():
     for step in range(args.steps):
         for sc in schemes:
             prob, res = hot_path(sc)
-            solves.append(dict(scheme=sc, status=res.status, iters=res.iters, solve_ms=res.solve_ms,
-                               true_relres=res.true_relres))
-            log("  step %d %s: status %d iters %d solve %.1f ms" % (step, sc, res.status, res.iters, res.solve_ms))
+            solves.append(dict(scheme=sc, status=res.status, iters=res.iters, restarts=res.restarts,
+                               solve_ms=res.solve_ms, true_relres=res.true_relres))
+            log("  step %d %s: status %d passes %d restarts %d solve %.1f ms true relres %.2e" %
+                (step, sc, res.status, res.iters, res.restarts, res.solve_ms, res.true_relres))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / max(args.steps, 1)
-    solve_s = float(np.mean([s["solve_ms"] for s in solves])) / 1e3
+    ok = [s for s in solves if s["status"] == adr.OK]
+    # value: mean time to tolerance over the solves that reached it on the true
+    # residual (ADR_OK); a solve that did not is reported, never averaged in
+    solve_s = float(np.mean([s["solve_ms"] for s in ok])) / 1e3 if ok else None
     iters = {sc: [s["iters"] for s in solves if s["scheme"] == sc] for sc in schemes}
     mean_iters = float(np.mean([s["iters"] for s in solves]))
     ms_per_iter = float(np.mean([s["solve_ms"] / max(s["iters"], 1) for s in solves]))
@@ -540,6 +604,17 @@ def main():
         raise RuntimeError("the solves did not use the stencil tables; the byte model below assumes them")
     algo_gbs = BYTES["iteration"] * N / (ms_per_iter * 1e-3) / 1e9
     dia_gbs = BYTES_DIA["iteration"] * N / (ms_per_iter * 1e-3) / 1e9
+
+    # ---- discretisation error and true residual of each FP64 form ----
+    forms = {}
+    for sc in schemes:
+        prob, res = hot_path(sc)
+        forms["fp64_" + sc] = solve_record(prob, res)
+        log("  fp64 %s: max error %.4e true relres %.2e" % (sc, forms["fp64_" + sc]["max_error"], res.true_relres))
+        if sc == "centered":
+            xref = res.x.clone()
+            ref_rec = forms["fp64_" + sc]
+        del prob, res
 
     # ---- per-kernel timing with HIP events on the library's stream ----
     log("kernel timing")
@@ -551,60 +626,55 @@ def main():
     times = kernel_us(prob, {"lsweep": lambda: prob.lsolve(q, out=y), "usweep": lambda: prob.usolve(y, out=z),
                              "spmv": lambda: prob.spmv(q, out=z)}, args.kernel_reps)
     for name, us in times.items():
-        b = BYTES[name] * N
-        kern[name] = dict(avg_us=us, algorithmic_bytes=b, gbs=b / (us * 1e-6) / 1e9)
-        log("  %s: %.1f us  %.0f GB/s" % (name, us, kern[name]["gbs"]))
+        b = BYTES_DIA[name] * N
+        kern[name] = dict(avg_us=us, algorithmic_bytes=b, gbs=b / (us * 1e-6) / 1e9,
+                          bytes_per_unknown=BYTES_DIA[name], bytes_per_unknown_read=BYTES[name],
+                          gbs_bytes_read=BYTES[name] * N / (us * 1e-6) / 1e9)
+        log("  %s: %.1f us  %.0f GB/s of %d B/unknown (%.0f GB/s of the %d B it reads)" %
+            (name, us, kern[name]["gbs"], BYTES_DIA[name], kern[name]["gbs_bytes_read"], BYTES[name]))
     dom = max(("lsweep", "usweep"), key=lambda k: kern[k]["avg_us"])
     traffic = traffic_for(dom, "n%d" % n)
-    # the bandwidth a plain element-wise copy reaches here (1 GiB read and
-    # 1 GiB written): a practical ceiling beside the 8 TB/s peak
-    a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-    bcp = torch.empty_like(a)
-    bcp.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        bcp.copy_(a)
-    e1.record()
-    e1.synchronize()
-    copy_gbs = 2 * a.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, bcp
-    log("  copy kernel: %.0f GB/s" % copy_gbs)
+    del prob
+    copy_gbs = copy_reference_gbs(dev)
+    log("  streaming copy kernel: %.0f GB/s" % copy_gbs)
     roofline = dict(bound="hbm", kernel=dom, achieved=round(kern[dom]["gbs"], 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(kern[dom]["gbs"] / PEAK_HBM_GBS, 4), traffic=traffic,
-                    bytes_per_unknown=BYTES[dom], unknowns_per_launch=N)
+                    bytes_per_unknown=BYTES_DIA[dom], unknowns_per_launch=N,
+                    bytes_per_unknown_read=BYTES[dom],
+                    frac_of_bytes_read=round(kern[dom]["gbs_bytes_read"] / PEAK_HBM_GBS, 4))
 
     # ---- mixed precision: FP32-stored factors (FP64 or FP32 sweeps) ----
     variants = {}
     if args.variants:
         log("mixed-precision variants")
-        ref_prob, ref = hot_path("centered")
-        xref = ref.x.clone()
+        e64 = ref_rec["max_error"]
         for prec in ("fp32_factors", "fp32_sweeps"):
-            prob = adr.assemble(args.eps, 1.0, 1.0, n, n, "centered", "dirichlet")
-            if args.rows:
-                prob.set_sweep_rows(args.rows)
-            prob.ilu0(prec)
-            res = prob.solve(tol=args.tol, maxit=args.maxit)
+            prob, res = hot_path("centered", maxit=args.variant_maxit, precision=prec)
             d = float((res.x - xref).abs().max() / xref.abs().max())
-            variants[prec] = dict(status=int(res.status), iters=int(res.iters), solve_s=round(res.solve_ms / 1e3, 4),
-                                  speedup_vs_fp64=round(ref.solve_ms / res.solve_ms, 3) if res.solve_ms > 0 else None,
-                                  max_rel_diff_vs_fp64=d, fp64_iters=int(ref.iters))
-            log("  %s: status %d iters %d (fp64 %d) %.2f s (fp64 %.2f s) max-rel-diff %.2e" %
-                (prec, res.status, res.iters, ref.iters, res.solve_ms / 1e3, ref.solve_ms / 1e3, d))
+            rec = solve_record(prob, res, dict(
+                speedup_vs_fp64=round(ref_rec["solve_s"] / (res.solve_ms / 1e3), 3) if res.solve_ms > 0 else None,
+                max_rel_diff_vs_fp64=d, fp64_iters=ref_rec["iters"]))
+            rec["max_error_within_1pct_of_fp64"] = bool(abs(rec["max_error"] - e64) <= 0.01 * e64)
+            variants[prec] = rec
+            log("  %s: status %d passes %d restarts %d (fp64 %d) %.2f s true relres %.2e max error %.4e "
+                "(fp64 %.4e) max-rel-diff %.2e" % (prec, res.status, res.iters, res.restarts, ref_rec["iters"],
+                                                  res.solve_ms / 1e3, res.true_relres, rec["max_error"], e64, d))
             del prob, res
-        del ref_prob, ref
 
     # ---- the Neumann variant over a fixed window of passes ----
     log("neumann window: %d passes" % args.neumann_window)
     neu = {}
     for sc in schemes:
+        c = adr.classify(args.eps, 1.0, 1.0, n, n, sc, "neumann")
         _, res = hot_path(sc, bc="neumann", maxit=args.neumann_window)
-        neu[sc] = dict(status=int(res.status), iters=int(res.iters), solve_ms=round(res.solve_ms, 2),
+        neu[sc] = dict(status=int(res.status), iters=int(res.iters), restarts=int(res.restarts),
+                       solve_ms=round(res.solve_ms, 2), true_relres=float(res.true_relres),
                        algorithmic_gbs=round(BYTES["iteration"] * N * res.iters / (res.solve_ms * 1e-3) / 1e9, 1)
                        if res.solve_ms > 0 and res.iters > 0 else None,
-                       last_relres=float(res.hist_l2[-1] / res.bnorm) if res.bnorm > 0 else None)
-        log("  %s: status %d iters %d" % (sc, res.status, res.iters))
+                       last_relres=float(res.hist_l2[-1] / res.bnorm) if res.bnorm > 0 else None,
+                       g_y=round(c.g_y, 2), expected_to_fail=c.expect_fail)
+        log("  %s: status %d passes %d (g_y %.1f, expected to fail: %s)" % (sc, res.status, res.iters, c.g_y,
+                                                                          c.expect_fail))
 
     # ---- CPU baseline: the oracle on a bounded sample ----
     cpu = None
@@ -634,7 +704,7 @@ def main():
         # the headline metric: time to tolerance of the plain FP64 solve, with the
         # achieved HBM GB/s and the mixed-precision variant alongside
         "metric": "time to rel-resid 1e-10 & HBM GB/s: plain FP64 vs mixed/batched/warm-start",
-        "value": round(solve_s, 4),
+        "value": round(solve_s, 4) if solve_s is not None else None,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -648,21 +718,24 @@ def main():
         "config": {"workload": "advection-diffusion %dx%d, X=Y=1, eps=%g, upwind+centered, "
                                "Dirichlet substitute for the Neumann mix (which does not converge)" % (n, n, args.eps),
                    "nx": n, "ny": n, "eps": args.eps, "tol": args.tol, "precision": args.precision,
-                   "sweep_rows": args.rows or "auto"},
+                   "sweep_rows": args.rows or "auto",
+                   "stop": "||r||_2 < tol ||b||_2 on the recursive residual, confirmed on the true residual "
+                           "b - A x (restart from x otherwise, up to 8 times)"},
+        "solves_ok": "%d of %d" % (len(ok), len(solves)),
         "iters": iters,
         "ms_per_iter": round(ms_per_iter, 4),
-        "bytes_per_unknown_per_pass": BYTES["iteration"],
-        "hbm_gbs_algorithmic": round(algo_gbs, 1),
-        "hbm_frac_algorithmic": round(algo_gbs / PEAK_HBM_GBS, 4),
+        "bytes_per_unknown_per_pass": BYTES_DIA["iteration"],
+        "bytes_per_unknown_per_pass_read": BYTES["iteration"],
+        "hbm_gbs_algorithmic": round(dia_gbs, 1),
+        "hbm_frac_algorithmic": round(dia_gbs / PEAK_HBM_GBS, 4),
+        "hbm_gbs_bytes_read": round(algo_gbs, 1),
         "copy_kernel_gbs": round(copy_gbs, 1),
-        "hbm_frac_of_copy_algorithmic": round(algo_gbs / copy_gbs, 4),
+        "hbm_frac_of_copy_algorithmic": round(dia_gbs / copy_gbs, 4),
         "roofline_frac_of_copy": round(kern[dom]["gbs"] / copy_gbs, 4),
-        # what a plain five-diagonal implementation would have to move per
-        # second to keep this pace (392 B per unknown per pass)
-        "hbm_gbs_dia_equivalent": round(dia_gbs, 1),
         "kernels": {k: {kk: round(vv, 2) for kk, vv in v.items()} for k, v in kern.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
         "mixed_precision": variants,
         "neumann_window": neu,
         "solves": solves,

@@ -226,8 +226,12 @@ adr_status adr_max_error(adr_problem *p, const double *x_dev, double *err_host);
  *   neg_offdiag  couplings between interior unknowns that are negative;
  *   nonneg_diag  unknowns whose diagonal C is >= 0 (sign change: ILU(0)
  *                pivots can pass through zero);
- *   expect_fail  1 if the solve is not expected to reach a small residual:
- *                Neumann data with g_y > 20, or nonneg_diag > 0.
+ *   expect_fail  1 if the solve is not expected to reach
+ *                ||b - A x|| < tol ||b||: Neumann data with g_y > ln(tol/u),
+ *                u = 2^-53 (the true residual cannot fall below about
+ *                u exp(g_y)); a diagonal that changes sign inside the grid;
+ *                or the upwind scheme (downwind for eq. (1)) with a negative
+ *                diagonal and a cell Peclet number above 2 (Section 6.3).
  * ------------------------------------------------------------------------- */
 typedef struct {
   double pe_x, pe_y, g_y;
@@ -237,7 +241,7 @@ typedef struct {
 } adr_instance_class;
 
 adr_status adr_classify(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme,
-                        int32_t bc, adr_instance_class *out);
+                        int32_t bc, double tol, adr_instance_class *out);
 
 /* Release every device resource of the problem (NULL is a no-op). */
 void adr_destroy(adr_problem *p);

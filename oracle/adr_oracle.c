@@ -280,9 +280,14 @@ int or_assemble(double eps, double X, double Y, int32_t nx, int32_t ny,
  *               (none: -A has the sign pattern of an M-matrix);
  *   nonneg_diag interior points with C >= 0 (the diagonal changes sign, and
  *               the ILU(0) pivots can pass through zero);
- *   expect_fail 1 if the solve is expected not to reach a small residual:
- *               Neumann data with g_y > 20, or a diagonal that is not
- *               negative everywhere.
+ *   expect_fail 1 if the solve is expected not to reach ||b - A x|| < tol ||b||:
+ *               - Neumann data with g_y > ln(tol / u), u = 2^-53: the true
+ *                 residual cannot fall below about u exp(g_y);
+ *               - a diagonal that changes sign inside the grid
+ *                 (0 < nonneg_diag < N);
+ *               - the upwind ("hybrid") scheme, whose backward differences
+ *                 are downwind for eq. (1), with a negative diagonal and a
+ *                 cell Peclet number above 2 (the Section 6.3 threshold).
  * Computed from the assembled five diagonals, point by point. */
 typedef struct {
   double pe_x, pe_y, g_y;
@@ -291,7 +296,7 @@ typedef struct {
 } or_class;
 
 int or_classify(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme, int32_t bc,
-                or_class *out) {
+                double tol, or_class *out) {
   memset(out, 0, sizeof(*out));
   if (!(eps > 0.0) || !(X > 0.0) || !(Y > 0.0) || nx < 1 || ny < 1 ||
       (scheme != 0 && scheme != 1) || (bc != 0 && bc != 1))
@@ -318,7 +323,11 @@ int or_classify(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t 
     out->neg_offdiag += (S[k] < 0.0) + (W[k] < 0.0) + (E[k] < 0.0) + (N[k] < 0.0);
     out->nonneg_diag += (C[k] >= 0.0);
   }
-  out->expect_fail = (bc == 1 && out->g_y > 20.0) || out->nonneg_diag > 0;
+  const double pe = out->pe_x > out->pe_y ? out->pe_x : out->pe_y;
+  const int neumann_floor = bc == 1 && tol > 0.0 && out->g_y > log(tol / ldexp(1.0, -53));
+  const int sign_change = out->nonneg_diag > 0 && out->nonneg_diag < (int64_t)n;
+  const int downwind = scheme == 0 && out->nonneg_diag == 0 && pe > 2.0;
+  out->expect_fail = neumann_floor || sign_change || downwind;
   free(S); free(W); free(C); free(E); free(N); free(r);
   return OR_OK;
 }

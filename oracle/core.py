@@ -56,7 +56,7 @@ def lib():
         L.or_assemble_data.restype = ctypes.c_int
         L.or_assemble_data.argtypes = [f64, f64, f64, i32, i32, i32, i32, _D, _D, f64] + [_D] * 10
         L.or_classify.restype = ctypes.c_int
-        L.or_classify.argtypes = [f64, f64, f64, i32, i32, i32, i32, ctypes.POINTER(_Class)]
+        L.or_classify.argtypes = [f64, f64, f64, i32, i32, i32, i32, f64, ctypes.POINTER(_Class)]
         L.or_spmv.argtypes = [i32, i32] + [_D] * 7
         L.or_ilu0.restype = ctypes.c_int
         L.or_ilu0.argtypes = [i32, i32] + [_D] * 8 + [ctypes.POINTER(i64)]
@@ -185,9 +185,9 @@ class Classification:
     expect_fail: bool
 
 
-def classify(eps, X, Y, nx, ny, scheme=UPWIND, bc=DIRICHLET):
+def classify(eps, X, Y, nx, ny, scheme=UPWIND, bc=DIRICHLET, tol=1e-10):
     c = _Class()
-    rc = lib().or_classify(float(eps), float(X), float(Y), int(nx), int(ny), int(scheme), int(bc),
+    rc = lib().or_classify(float(eps), float(X), float(Y), int(nx), int(ny), int(scheme), int(bc), float(tol),
                            ctypes.byref(c))
     if rc != OK:
         raise ValueError("or_classify rejected its arguments (status %d)" % rc)

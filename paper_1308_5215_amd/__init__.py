@@ -295,12 +295,13 @@ class InstanceClass:
     expect_fail: bool
 
 
-def classify(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet"):
-    """What an instance's discretisation looks like before it is solved
-    (adr_classify; Section 6.3 mesh Reynolds number)."""
+def classify(eps, X, Y, nx, ny, scheme="upwind", bc="dirichlet", tol=1e-10):
+    """What an instance's discretisation looks like before it is solved, and
+    whether a solve to tol is expected to fail (adr_classify; Section 6.3
+    mesh Reynolds number)."""
     c = _lib.InstanceClass()
     _lib.check(_lib.load().adr_classify(float(eps), float(X), float(Y), int(nx), int(ny), _SCHEMES[scheme],
-                                        _BCS[bc], ctypes.byref(c)))
+                                        _BCS[bc], float(tol), ctypes.byref(c)))
     return InstanceClass(c.pe_x, c.pe_y, c.g_y, c.neg_offdiag, c.nonneg_diag, bool(c.expect_fail))
 
 

@@ -157,7 +157,7 @@ def load():
     L.adr_max_error.restype = ctypes.c_int
     L.adr_max_error.argtypes = [P, P, D]
     L.adr_classify.restype = ctypes.c_int
-    L.adr_classify.argtypes = [f64, f64, f64, i32, i32, i32, i32, ctypes.POINTER(InstanceClass)]
+    L.adr_classify.argtypes = [f64, f64, f64, i32, i32, i32, i32, f64, ctypes.POINTER(InstanceClass)]
     L.adr_stream_copy.restype = ctypes.c_int
     L.adr_stream_copy.argtypes = [P, P, i64, P]
     L.adr_dot_noalloc.restype = ctypes.c_int

@@ -1221,7 +1221,7 @@ adr_status adr_max_error(adr_problem *P, const double *x, double *err_host) {
 }
 
 adr_status adr_classify(double eps, double X, double Y, int32_t nx, int32_t ny, int32_t scheme, int32_t bc,
-                        adr_instance_class *out) {
+                        double tol, adr_instance_class *out) {
   g_last_error.clear();
   if (!out) return fail(ADR_ERR_ARG, "out is NULL");
   memset(out, 0, sizeof(*out));
@@ -1230,6 +1230,7 @@ adr_status adr_classify(double eps, double X, double Y, int32_t nx, int32_t ny, 
   if (nx < 1 || ny < 1) return fail(ADR_ERR_ARG, "nx and ny must be >= 1 (got %d, %d)", nx, ny);
   if (scheme != ADR_UPWIND && scheme != ADR_CENTERED) return fail(ADR_ERR_ARG, "unknown scheme %d", scheme);
   if (bc != ADR_BC_DIRICHLET && bc != ADR_BC_NEUMANN_XY) return fail(ADR_ERR_ARG, "unknown bc %d", bc);
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(ADR_ERR_ARG, "tol must be finite and >= 0 (got %g)", tol);
   // the Section 4 coefficients, per column (through a) and per row (through
   // b), evaluated as the assembly kernel evaluates them
   const double dx = X / (double)(nx + 1), dy = Y / (double)(ny + 1);
@@ -1280,7 +1281,14 @@ adr_status adr_classify(double eps, double X, double Y, int32_t nx, int32_t ny, 
     }
   }
   out->nonneg_diag = nonneg;
-  out->expect_fail = ((bc == ADR_BC_NEUMANN_XY && out->g_y > 20.0) || nonneg > 0) ? 1 : 0;
+  // expected failures: the Neumann residual floor u exp(g_y) above tol; a
+  // diagonal that changes sign inside the grid (pivots through zero); the
+  // downwind-differenced upwind scheme beyond cell Peclet 2
+  const int64_t npts = (int64_t)nx * ny;
+  const bool floor_above_tol = bc == ADR_BC_NEUMANN_XY && tol > 0.0 && out->g_y > std::log(tol / std::ldexp(1.0, -53));
+  const bool sign_change = nonneg > 0 && nonneg < npts;
+  const bool downwind = scheme == ADR_UPWIND && nonneg == 0 && std::max(out->pe_x, out->pe_y) > 2.0;
+  out->expect_fail = (floor_above_tol || sign_change || downwind) ? 1 : 0;
   return ADR_OK;
 }
 

@@ -183,9 +183,30 @@ def test_diagonal_sign_counted_in_closed_form(orc):
 
 
 def test_expectation_rule(orc):
-    assert orc.classify(0.01, 1.0, 1.0, 256, 256, core.CENTERED, core.NEUMANN).expect_fail      # g_y = 63
-    assert not orc.classify(0.1, 1.0, 1.0, 256, 256, core.CENTERED, core.NEUMANN).expect_fail   # g_y = 6.3
-    assert not orc.classify(0.01, 1.0, 1.0, 256, 256, core.CENTERED, core.DIRICHLET).expect_fail
+    """The three failure mechanisms: the Neumann residual floor u exp(g_y)
+    against tol (threshold ln(tol/u) = 13.71 at tol 1e-10, 9.11 at 1e-12),
+    a diagonal that changes sign inside the grid, and downwind differencing
+    beyond cell Peclet 2."""
+    u = 2.0 ** -53
+    assert math.log(1e-10 / u) == pytest.approx(13.7109, abs=1e-4)
+    # g_y = (1 - e^-1) / eps: 13.0 at eps = 0.048626, 14.0 at 0.045153
+    for eps, gy in ((0.048626, 13.0), (0.045153, 14.0)):
+        c = orc.classify(eps, 1.0, 1.0, 64, 64, core.CENTERED, core.NEUMANN, tol=1e-10)
+        assert c.g_y == pytest.approx(gy, rel=1e-4)
+        assert c.expect_fail == (gy > 13.7109)
+        assert orc.classify(eps, 1.0, 1.0, 64, 64, core.CENTERED, core.NEUMANN, tol=1e-12).expect_fail
+        assert not orc.classify(eps, 1.0, 1.0, 64, 64, core.CENTERED, core.DIRICHLET, tol=1e-12).expect_fail
+    # diagonal sign change inside the grid (see the closed-form count above)
+    assert orc.classify(0.0133, 1.0, 1.0, 40, 40, core.UPWIND, core.DIRICHLET).expect_fail
+    # downwind: upwind scheme, negative diagonal, Peclet 1.5 (fine) and 2.5 (not)
+    for pe, fails in ((1.5, False), (2.5, True)):
+        n = 99
+        h = 1.0 / (n + 1)
+        eps = 2.0 * h / pe      # max a = 1 + (n h)^2 ~ 2
+        c = orc.classify(eps, 1.0, 1.0, n, n, core.UPWIND, core.DIRICHLET)
+        assert c.nonneg_diag == 0 and c.pe_x == pytest.approx(pe, rel=0.02)
+        assert c.expect_fail == fails
+        assert not orc.classify(eps, 1.0, 1.0, n, n, core.CENTERED, core.DIRICHLET).expect_fail
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(os.path.dirname(HERE), "paper_1308_5215_amd", "libadr.so")),
@@ -200,8 +221,9 @@ def test_library_classifier_equals_the_oracle(orc):
         X, Y = rng.uniform(0.5, 2.0, 2)
         nx, ny = (int(v) for v in rng.integers(1, 120, 2))
         sc, bc = (int(v) for v in rng.integers(0, 2, 2))
-        a = adr.classify(eps, X, Y, nx, ny, sc, bc)
-        b = orc.classify(eps, X, Y, nx, ny, sc, bc)
+        tol = 10 ** rng.uniform(-13, -6)
+        a = adr.classify(eps, X, Y, nx, ny, sc, bc, tol)
+        b = orc.classify(eps, X, Y, nx, ny, sc, bc, tol)
         assert (a.neg_offdiag, a.nonneg_diag, a.expect_fail) == (b.neg_offdiag, b.nonneg_diag, b.expect_fail)
         assert a.pe_x == pytest.approx(b.pe_x, rel=1e-14) and a.pe_y == pytest.approx(b.pe_y, rel=1e-14)
         assert a.g_y == pytest.approx(b.g_y, rel=1e-14)
