@@ -202,7 +202,18 @@ struct adr_problem {
   const double *stencil_tab() const { return (has_tab && tab_on) ? tab : nullptr; }
   // automatic: compact once the strips exceed 1.5 per CU (384 on 256 CUs)
   int ring_compact() const { return compact >= 0 ? compact : (2 * nstrips > 3 * cus ? 1 : 0); }
-  BatchGeom geom() const { return BatchGeom{d_inst, count, nblk, nstrips, rows, ring_compact()}; }
+  // XCD-grouped strips: a single instance whose strips all fit on the
+  // device at once (one workgroup per CU on the deep ring) places
+  // consecutive strips on one XCD (workgroup b runs on XCD b mod 8)
+  int xcd_group() const {
+#ifdef ADR_NO_XCD_GROUPS
+    return 0;
+#else
+    if (count != 1 || ring_compact() || rows != 31 || nstrips > cus) return 0;
+    return (nstrips + 7) / 8;
+#endif
+  }
+  BatchGeom geom() const { return BatchGeom{d_inst, count, nblk, nstrips, rows, ring_compact(), xcd_group()}; }
 };
 
 namespace {

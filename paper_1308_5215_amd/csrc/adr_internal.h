@@ -83,6 +83,7 @@ struct BatchGeom {
   int nstrips;        // total strips
   int rows;           // strip height R
   int compact;        // 31-row sweeps: 76 KB ring, two workgroups per CU (see adr_sweeps.hip)
+  int xcd_group;      // > 0: strips by workgroup index, xcd_group consecutive strips per XCD
 };
 
 // Single-instance streaming geometry (assembly, diagnostics).

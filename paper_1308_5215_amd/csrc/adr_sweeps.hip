@@ -35,6 +35,16 @@ namespace adr {
 namespace {
 
 constexpr unsigned SPIN_LIMIT = 1u << 20;   // polls before a wait is declared failed
+#ifndef ADR_SWEEP_THREADS
+#define ADR_SWEEP_THREADS 512
+#endif
+#ifndef ADR_LOADER_DEPTH
+#define ADR_LOADER_DEPTH 2
+#endif
+// chunks of loads in flight per loader wave: two where one workgroup holds
+// the CU (31-row strips, deep ring: 256 registers per wave), one where two
+// workgroups share it (128 registers per wave)
+constexpr int LDEPTH_DEEP = ADR_LOADER_DEPTH;
 
 __device__ __forceinline__ double dpp_up(double v) {
   // lane l receives lane l-1's value; lane 0 receives 0
@@ -78,6 +88,46 @@ __device__ __forceinline__ double handoff_take(const uint64_t *p, bool need, uin
   if (need && b == HANDOFF_EMPTY) b = 0;
   if (need) __hip_atomic_store(const_cast<uint64_t *>(p), HANDOFF_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return need ? __longlong_as_double((long long)b) : 0.0;
+}
+
+// Pair loads for the loader waves: one 16-byte (FP64) or 8-byte (FP32) load
+// of two adjacent row elements, aligned to the element only. The per-CU
+// memory pipeline issues whole instructions at a fixed rate, so two elements
+// per lane halve the instruction count.
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+template <class T>
+struct Pair {
+  T x, y;   // the lane's first and second tile column
+};
+__device__ __forceinline__ int64_t rfl64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v), hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// Buffer resource of the raw byte range [base, base + bytes), bytes < 2^32
+// (gfx9 descriptor word 3: 32-bit data, no swizzle).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)(unsigned)bytes, 0x00020000);
+}
+// elements e + s and e + s + 1 of a buffer of T: lane offset e (a VGPR that
+// stays put), uniform offset s (an SGPR per chunk); no address arithmetic
+template <class T>
+__device__ __forceinline__ Pair<T> ld_pair_buf(__amdgpu_buffer_rsrc_t r, unsigned e, int s) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  if constexpr (sizeof(T) == 8) {
+    const d2 v = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)(e * 8u), s * 8, 0));
+    return Pair<T>{v.x, v.y};
+  } else {
+    const f2 v = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 4u), s * 4, 0));
+    return Pair<T>{v.x, v.y};
+  }
+}
+// the same pair with its elements swapped (the U sweep walks columns from
+// the right, so its first tile column is the higher grid column)
+template <class T>
+__device__ __forceinline__ Pair<T> swap_pair(Pair<T> r) {
+  return Pair<T>{r.y, r.x};
 }
 
 // Instance owning global strip t (instances sorted by strip0).
@@ -168,7 +218,7 @@ struct SweepShape {
   static constexpr int W = 16;                      // columns per chunk
   static constexpr int L = R + 1;                   // tile rows (row 0 = ghost)
   static constexpr int PITCH = W + 2;               // 16-byte aligned rows
-  static constexpr int NT = 512;                    // threads per workgroup
+  static constexpr int NT = ADR_SWEEP_THREADS;      // threads per workgroup
   static constexpr int NLD = NT / 64 - 3;           // loader waves
   // 76 KB (two workgroups per CU) for R = 15 and for compact 31-row strips
   // (tiles of at most three arrays, four or more slots), else 150 KB (one
@@ -186,7 +236,7 @@ struct SweepShape {
 }  // namespace
 
 template <int R, int OP, int PREC, bool TAB, bool CMP>
-__global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
+__global__ __launch_bounds__(ADR_SWEEP_THREADS) void k_sweep_ws(SweepParams p) {
   static_assert(!TAB || OP == 1 || PREC == 0, "the L sweep forms its factors from tables only in FP64");
   using TF = typename std::conditional<PREC == 0, double, float>::type;
   using CT = typename std::conditional<PREC == 2, float, double>::type;
@@ -198,6 +248,7 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   using Sh = SweepShape<R, NL, (int)sizeof(CT), CMP>;
   constexpr int W = Sh::W, L = Sh::L, PITCH = Sh::PITCH, NC = Sh::NC, NT = Sh::NT, NLD = Sh::NLD;
   constexpr int RPP = Sh::RPP, NP = Sh::NP;
+  constexpr int LDEPTH = (R > 15 && !CMP) ? LDEPTH_DEEP : 1;
   static_assert(L <= 64, "strip too tall");
   __shared__ __align__(16) CT s_in[NC][NL][L][PITCH];
   __shared__ __align__(16) double s_out[2][L][PITCH];
@@ -205,8 +256,21 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
   __shared__ int s_computed, s_stored;
   __shared__ int s_strip, s_inst;
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (tid == 0) {
+  // wave index and everything derived from the strip are wave-uniform; say
+  // so (readfirstlane), so that branches on them stay scalar
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  if (p.g.xcd_group > 0) {
+    // strips by workgroup index: XCD x = b mod 8 holds strips
+    // [x G, x G + G); every strip is resident, so any wait ends
+    const int b = blockIdx.x, t = (b & 7) * p.g.xcd_group + (b >> 3);
+    if (t >= p.g.nstrips) return;   // padding workgroup: no strip
+    if (tid == 0) {
+      s_inst = 0;
+      s_strip = t;
+      s_computed = 0;
+      s_stored = 0;
+    }
+  } else if (tid == 0) {
     const int t = (int)atomicAdd(&p.sync.ticket[0], 1u);
     const int ii = find_strip_inst(p.g.inst, p.g.ninst, t);
     s_inst = ii;
@@ -224,31 +288,227 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
     s_in[sl][m][0][w] = (OP == 1 && m == NL - 1) ? (CT)1 : (CT)0;
   }
   __syncthreads();
-  const int strip = s_strip;
-  const Inst I = p.g.inst[s_inst];
+  const int strip = __builtin_amdgcn_readfirstlane(s_strip);
+  const int sinst = __builtin_amdgcn_readfirstlane(s_inst);
+  // the instance record, read with vector loads, made wave-uniform
+  const Inst I = p.g.inst[sinst];
+  const int64_t ioff = rfl64(I.off), itab = rfl64(I.tab_off), iho = rfl64(I.ho_off);
   // RUNNING: a pass; CHECK: the first pass of a possible restart (M^{-1} of
   // the true residual); any other phase: this instance has stopped
-  if (p.st && p.st[s_inst].phase != RUNNING && p.st[s_inst].phase != CHECK) {
+  if (p.st && p.st[sinst].phase != RUNNING && p.st[sinst].phase != CHECK) {
     strip_finish(p.sync, p.g.nstrips);
     return;
   }
-  const int nx = I.nx, ny = I.ny;
+  const int nx = __builtin_amdgcn_readfirstlane(I.nx), ny = __builtin_amdgcn_readfirstlane(I.ny);
   const int base = strip * R;
   const int rows = min(R, ny - base);
   const bool has_prev = strip > 0, has_next = base + R < ny;
   const int nchunks = (nx + rows + W - 1) / W;
   const int lr = lane / W, lc = lane % W;   // tile (row-in-pass, column) for loads and stores
-  const double *vin = p.v + I.off;
-  double *vout = p.out + I.off;
-  const uint64_t *ho_base = p.sync.handoff + I.ho_off;
+  const double *vin = p.v + ioff;
+  double *vout = p.out + ioff;
+  const uint64_t *ho_base = p.sync.handoff + iho;
   auto grow = [&](int l) { return OP == 0 ? base + l - 1 : ny - base - l; };
   auto gcol = [&](int co) { return OP == 0 ? co : nx - 1 - co; };
 
-  if (wave >= 3) {
-    // ------------------------------------------------------------ loaders
-    const TF *f1 = (const TF *)p.f1 + I.off, *f2 = (const TF *)p.f2 + I.off, *f3 = (const TF *)p.f3 + I.off;
+  if (wave >= 3 && nx >= 2) {
+    // ------------------------------------------------------- pair loaders
+    // A lane holds two adjacent columns of one tile row per array (8 lanes
+    // per row, 8 rows per pass).
+    const TF *f1 = (const TF *)p.f1 + ioff, *f2 = (const TF *)p.f2 + ioff, *f3 = (const TF *)p.f3 + ioff;
+    const double *tab = TAB ? p.tab + itab : nullptr;
+    constexpr int RP2 = 8, NP2 = (L - 1 + RP2 - 1) / RP2;
+    const int lr2 = lane >> 3, tc = 2 * (lane & 7);
+    double rowv[TAB ? NP2 : 1];
+    if (TAB) {
+#pragma unroll
+      for (int q = 0; q < NP2; ++q) {
+        const int l = 1 + q * RP2 + lr2;
+        const int gj = (l <= rows) ? grow(l) : 0;
+        rowv[q] = tab[2 * nx + (OP == 0 ? 0 : ny) + gj];
+      }
+    }
+    // Interior chunks take a fast path: chunks c in [cf0, cf1] of a full
+    // strip have every column of every tile row inside the grid (and, for
+    // the table-driven L sweep, its left neighbour too), so each pair window
+    // moves by a fixed 16 elements per chunk and nothing is masked. Lane
+    // offsets are taken at an anchor chunk (cf0 for L, cf1 for U) where all
+    // of them are >= 0 and fit 32 bits; the chunk adds a uniform shift >= 0
+    // (buffer loads: lane offset in a VGPR, shift in an SGPR).
+    // Rows past the strip (l = L) reuse row L-1; they are never stored.
+    // Edge chunks load each element at its clamped column and are masked in
+    // commit, which recomputes the masks (no lane masks live across a tile).
+    const int cf0 = (R + 16) / 16, cf1 = (nx - 15) / 16;
+    const bool fastok = rows == L - 1 && (size_t)nx * ny < ((size_t)1 << 29);
+    unsigned ek[NP2], eks[NP2], et[NP2];   // element offsets: row, row below, table
+#pragma unroll
+    for (int q = 0; q < NP2; ++q) {
+      const int l = min(1 + q * RP2 + lr2, L - 1);
+      const int gj = grow(l);
+      const int o = OP == 0 ? tc - l + 16 * cf0 : nx - 2 - tc + l - 16 * cf1;
+      et[q] = (unsigned)o;
+      ek[q] = (unsigned)(gj * nx + o);
+      eks[q] = (unsigned)((gj > 0 ? gj - 1 : gj) * nx + o);
+    }
+    const size_t abytes = (size_t)nx * ny * sizeof(double), fbytes = (size_t)nx * ny * sizeof(TF);
+    const __amdgpu_buffer_rsrc_t rv = raw_rsrc(vin, abytes);
+    const __amdgpu_buffer_rsrc_t r1 = raw_rsrc(f1, fbytes), r2 = raw_rsrc(f2, fbytes), r3 = raw_rsrc(f3, fbytes);
+    const __amdgpu_buffer_rsrc_t rt = raw_rsrc(TAB ? tab : vin, TAB ? (size_t)(2 * nx + 2 * ny) * sizeof(double) : 0);
+    struct Tile2 {
+      bool fast;
+      Pair<double> v[NP2];                 // q (L) or y (U)
+      Pair<TF> f[NIN - 1][NP2];            // factor arrays (non-TAB), invd (U TAB)
+      Pair<double> t[NP2];                 // the column table: W (L TAB) or E (U TAB)
+      Pair<double> iw[TAB && OP == 0 ? NP2 : 1], is[TAB && OP == 0 ? NP2 : 1];
+    };
+    auto issue = [&](Tile2 &T, int c) {
+      T.fast = fastok && c >= cf0 && c <= cf1;
+      if (T.fast) {
+        const int sh = OP == 0 ? 16 * (c - cf0) : 16 * (cf1 - c);
+        auto ld = [&](auto tag, __amdgpu_buffer_rsrc_t r, unsigned e, int s) {
+          using E = decltype(tag);
+          return OP == 0 ? ld_pair_buf<E>(r, e, s) : swap_pair(ld_pair_buf<E>(r, e, s));
+        };
+#pragma unroll
+        for (int q = 0; q < NP2; ++q) {
+          T.v[q] = ld(double(), rv, ek[q], sh);
+          if (TAB && OP == 0) {
+            T.iw[q] = ld(double(), r3, ek[q] - 1, sh);    // invd
+            T.is[q] = ld(double(), r3, eks[q], sh);
+            T.t[q] = ld(double(), rt, et[q], sh);         // W(i)
+          } else if (TAB) {
+            T.t[q] = ld(double(), rt, et[q], nx + sh);    // E(i)
+            T.f[NIN - 2][q] = ld(TF(), r3, ek[q], sh);
+          } else {
+            T.f[0][q] = ld(TF(), r1, ek[q], sh);
+            T.f[1][q] = ld(TF(), r2, ek[q], sh);
+            if (NIN == 4) T.f[NIN - 2][q] = ld(TF(), r3, ek[q], sh);
+          }
+        }
+        return;
+      }
+#pragma unroll
+      for (int q = 0; q < NP2; ++q) {
+        const int l = 1 + q * RP2 + lr2;
+        const int co0 = c * W + tc - l;
+        const int gj = (l <= rows) ? grow(l) : 0;
+        // grid columns of the lane's two tile columns, clamped into the row
+        const int g0 = gcol(max(0, min(co0, nx - 1))), g1 = gcol(max(0, min(co0 + 1, nx - 1)));
+        const size_t rb = (size_t)gj * nx;
+        T.v[q].x = vin[rb + g0];
+        T.v[q].y = vin[rb + g1];
+        if (TAB && OP == 0) {
+          // lw = W(i) invd(k-1) for i > 0, ls = S(j) invd(k-nx) for j > 0, else 0
+          const double *invd = (const double *)f3;
+          const size_t rs = gj > 0 ? rb - nx : rb;
+          T.iw[q].x = invd[rb + max(g0 - 1, 0)];
+          T.iw[q].y = invd[rb + max(g1 - 1, 0)];
+          T.is[q].x = invd[rs + g0];
+          T.is[q].y = invd[rs + g1];
+          T.t[q].x = tab[g0];                        // W(i)
+          T.t[q].y = tab[g1];
+        } else if (TAB) {
+          T.t[q].x = tab[nx + g0];                   // E(i)
+          T.t[q].y = tab[nx + g1];
+          T.f[NIN - 2][q].x = f3[rb + g0];
+          T.f[NIN - 2][q].y = f3[rb + g1];
+        } else {
+#pragma unroll
+          for (int m = 0; m < NIN - 1; ++m) {
+            const TF *fm = m == 0 ? f1 : (m == 1 ? f2 : f3);
+            T.f[m][q].x = fm[rb + g0];
+            T.f[m][q].y = fm[rb + g1];
+          }
+        }
+      }
+    };
+    auto commit = [&](Tile2 &T, int c) {
+      // element values of the tile's arrays, masked on edge chunks
+      CT v0[NP2][2];
+      TF bf[NIN - 1][NP2][2];
+      auto values = [&](auto fastc) {
+        constexpr bool fast = decltype(fastc)::value;
+#pragma unroll
+      for (int q = 0; q < NP2; ++q) {
+        const int l = 1 + q * RP2 + lr2;
+        const int gj = (l <= rows) ? grow(l) : 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int co = c * W + tc - l + h;
+          const bool ok = fast || (l <= rows && co >= 0 && co < nx);
+          const double v = h == 0 ? T.v[q].x : T.v[q].y;
+          v0[q][h] = ok ? (CT)v : (CT)0;
+          if (TAB && OP == 0) {
+            const bool fi = fast || gcol(co) > 0, fj = gj > 0;
+            const double t = h == 0 ? T.t[q].x : T.t[q].y;
+            const double iw = h == 0 ? T.iw[q].x : T.iw[q].y, is = h == 0 ? T.is[q].x : T.is[q].y;
+            bf[0][q][h] = ok && fi ? (TF)(t * iw) : (TF)0;
+            bf[1][q][h] = ok && fj ? (TF)(rowv[q] * is) : (TF)0;
+          } else if (TAB) {
+            bf[0][q][h] = ok ? (TF)(h == 0 ? T.t[q].x : T.t[q].y) : (TF)0;   // E(i)
+            bf[1][q][h] = ok ? (TF)rowv[q] : (TF)0;                          // N(j)
+            bf[NIN - 2][q][h] = ok ? (h == 0 ? T.f[NIN - 2][q].x : T.f[NIN - 2][q].y) : (TF)0;
+          } else {
+#pragma unroll
+            for (int m = 0; m < NIN - 1; ++m)
+              bf[m][q][h] = ok ? (h == 0 ? T.f[m][q].x : T.f[m][q].y) : (TF)0;
+          }
+        }
+      }
+      };
+      if (T.fast) values(std::true_type{});
+      else values(std::false_type{});
+      lds_wait_ge(&s_computed, c - NC + 1);   // ring slot free
+      const int sl = c % NC;
+#pragma unroll
+      for (int q = 0; q < NP2; ++q) {
+        const int l = 1 + q * RP2 + lr2;
+        if (l < L) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            s_in[sl][0][l][tc + h] = v0[q][h];
+#pragma unroll
+            for (int m = 1; m < NIN; ++m) {
+              if (NREG && m == 2) continue;   // N: the compute wave's register
+              s_in[sl][(NREG && m == 3) ? 2 : m][l][tc + h] = (CT)bf[m - 1][q][h];
+            }
+          }
+        }
+      }
+      lds_put(&s_flag[sl][0], c + 1);
+    };
+    if (LDEPTH == 1) {
+      for (int c = wave - 3; c < nchunks; c += NLD) {
+        Tile2 T;
+        issue(T, c);
+        commit(T, c);
+      }
+    } else {
+      // the scheduling barriers keep each tile's loads together and ahead of
+      // the next tile's, so a commit waits for its own tile only
+      Tile2 A, B;
+      int c = wave - 3;
+      if (c < nchunks) issue(A, c);
+      __builtin_amdgcn_sched_barrier(0);
+      while (c < nchunks) {
+        issue(B, c + NLD);
+        __builtin_amdgcn_sched_barrier(0);
+        commit(A, c);
+        __builtin_amdgcn_sched_barrier(0);
+        c += NLD;
+        if (c >= nchunks) break;
+        issue(A, c + NLD);
+        __builtin_amdgcn_sched_barrier(0);
+        commit(B, c);
+        __builtin_amdgcn_sched_barrier(0);
+        c += NLD;
+      }
+    }
+  } else if (wave >= 3) {
+    // ---------------------------------------- element loaders (nx == 1)
+    const TF *f1 = (const TF *)p.f1 + ioff, *f2 = (const TF *)p.f2 + ioff, *f3 = (const TF *)p.f3 + ioff;
     // stencil tables of the instance: Wc[nx], Ec[nx], Sr[ny], Nr[ny]
-    const double *tab = TAB ? p.tab + I.tab_off : nullptr;
+    const double *tab = TAB ? p.tab + itab : nullptr;
     // the row entry (S for L, N for U) of each strip row this lane loads is
     // the same in every chunk: read once
     double rowv[TAB ? NP : 1];
@@ -260,15 +520,19 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
         rowv[q] = tab[2 * nx + (OP == 0 ? 0 : ny) + gj];
       }
     }
-    for (int c = wave - 3; c < nchunks; c += NLD) {
-      // every load of the tile is issued before any is used (points outside
-      // the strip load element 0 and are zeroed afterwards), so the loads
-      // overlap one another and the wait for the ring slot
+    // A loader keeps LDEPTH of its chunks in flight: the loads of the next
+    // chunk it owns are issued before the previous one is written to the
+    // ring, so each loader wave has up to LDEPTH tiles of loads outstanding.
+    // Every load of a tile is issued before any is used (points outside the
+    // strip load element 0 and are zeroed afterwards).
+    struct Tile {
       double bv[NP];
       TF bf[NIN - 1][NP];
       bool okq[NP];
       double iw[TAB && OP == 0 ? NP : 1], is[TAB && OP == 0 ? NP : 1];   // invd of the x- and y-predecessor
       int fi[TAB && OP == 0 ? NP : 1], fj[TAB && OP == 0 ? NP : 1];
+    };
+    auto issue = [&](Tile &T, int c) {
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const int l = 1 + q * RPP + lr;
@@ -276,32 +540,34 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
         const bool ok = (l <= rows) && (co >= 0) && (co < nx);
         const int gi = ok ? gcol(co) : 0, gj = ok ? grow(l) : 0;
         const size_t k = (size_t)gj * nx + gi;
-        okq[q] = ok;
-        bv[q] = vin[k];
+        T.okq[q] = ok;
+        T.bv[q] = vin[k];
         if (TAB && OP == 0) {
           // lw = W(i) invd(k-1) for i > 0, ls = S(j) invd(k-nx) for j > 0, else 0
           const double *invd = (const double *)f3;
-          iw[q] = invd[gi > 0 ? k - 1 : k];
-          is[q] = invd[gj > 0 ? k - nx : k];
-          bf[0][q] = (TF)tab[gi];           // W(i)
-          bf[1][q] = (TF)rowv[q];           // S(j)
-          fi[q] = gi;
-          fj[q] = gj;
+          T.iw[q] = invd[gi > 0 ? k - 1 : k];
+          T.is[q] = invd[gj > 0 ? k - nx : k];
+          T.bf[0][q] = (TF)tab[gi];           // W(i)
+          T.bf[1][q] = (TF)rowv[q];           // S(j)
+          T.fi[q] = gi;
+          T.fj[q] = gj;
         } else if (TAB) {
-          bf[0][q] = (TF)tab[nx + gi];      // E(i)
-          bf[1][q] = (TF)rowv[q];           // N(j)
-          bf[NIN - 2][q] = f3[k];
+          T.bf[0][q] = (TF)tab[nx + gi];      // E(i)
+          T.bf[1][q] = (TF)rowv[q];           // N(j)
+          T.bf[NIN - 2][q] = f3[k];
         } else {
-          bf[0][q] = f1[k];
-          bf[1][q] = f2[k];
-          if (NIN == 4) bf[NIN - 2][q] = f3[k];
+          T.bf[0][q] = f1[k];
+          T.bf[1][q] = f2[k];
+          if (NIN == 4) T.bf[NIN - 2][q] = f3[k];
         }
       }
+    };
+    auto commit = [&](Tile &T, int c) {
       if (TAB && OP == 0) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          bf[0][q] = fi[q] > 0 ? (TF)((double)bf[0][q] * iw[q]) : (TF)0;
-          bf[1][q] = fj[q] > 0 ? (TF)((double)bf[1][q] * is[q]) : (TF)0;
+          T.bf[0][q] = T.fi[q] > 0 ? (TF)((double)T.bf[0][q] * T.iw[q]) : (TF)0;
+          T.bf[1][q] = T.fj[q] > 0 ? (TF)((double)T.bf[1][q] * T.is[q]) : (TF)0;
         }
       }
       lds_wait_ge(&s_computed, c - NC + 1);   // ring slot free
@@ -310,15 +576,39 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
       for (int q = 0; q < NP; ++q) {
         const int l = 1 + q * RPP + lr;
         if (l < L) {
-          s_in[sl][0][l][lc] = okq[q] ? (CT)bv[q] : (CT)0;
+          s_in[sl][0][l][lc] = T.okq[q] ? (CT)T.bv[q] : (CT)0;
 #pragma unroll
           for (int m = 1; m < NIN; ++m) {
             if (NREG && m == 2) continue;   // N: the compute wave's register
-            s_in[sl][(NREG && m == 3) ? 2 : m][l][lc] = okq[q] ? (CT)bf[m - 1][q] : (CT)0;
+            s_in[sl][(NREG && m == 3) ? 2 : m][l][lc] = T.okq[q] ? (CT)T.bf[m - 1][q] : (CT)0;
           }
         }
       }
       lds_put(&s_flag[sl][0], c + 1);
+    };
+    if (LDEPTH == 1) {
+      for (int c = wave - 3; c < nchunks; c += NLD) {
+        Tile T;
+        issue(T, c);
+        commit(T, c);
+      }
+    } else {
+      // The next tile's loads are issued whether or not that chunk exists (a
+      // chunk past the end has no point in the strip: its lanes load element
+      // 0 and it is never committed), so the number of loads in flight is the
+      // same on every path and each commit waits only for its own tile.
+      Tile A, B;
+      int c = wave - 3;
+      if (c < nchunks) issue(A, c);
+      while (c < nchunks) {
+        issue(B, c + NLD);
+        commit(A, c);
+        c += NLD;
+        if (c >= nchunks) break;
+        issue(A, c + NLD);
+        commit(B, c);
+        c += NLD;
+      }
     }
   } else if (wave == 1) {
     // ------------------------------------------------------------- poller
@@ -387,12 +677,19 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
     for (int c = 0; c < nchunks; ++c) {
       lds_wait_ge(&s_computed, c + 1);
       const int b = c & 1;
+      // every LDS read of the tile first (one wait), then the stores
+      double o[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int l = 1 + q * RPP + lr;
+        o[q] = s_out[b][l < L ? l : L - 1][lc];
+      }
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const int l = 1 + q * RPP + lr;
         const int co = c * W + lc - l;
         const bool ok = (l <= rows) && (co >= 0) && (co < nx);
-        if (ok) vout[(size_t)grow(l) * nx + gcol(co)] = s_out[b][l][lc];
+        if (ok) vout[(size_t)grow(l) * nx + gcol(co)] = o[q];
       }
       lds_put(&s_stored, c + 1);
     }
@@ -407,7 +704,7 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
     // (NaN only if the neighbour in x already is), as with a zero N.
     CT nrow = (CT)0;
     if (NREG && lane >= 1 && lane < L && lane <= rows)
-      nrow = (CT)(TF)p.tab[I.tab_off + 2 * nx + ny + grow(lane)];
+      nrow = (CT)(TF)p.tab[itab + 2 * nx + ny + grow(lane)];
     CT west = (CT)0;
     uint64_t fl = lds_peek_pair(&s_flag[0][0]);
     for (int c = 0; c < nchunks; ++c) {
@@ -415,12 +712,14 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
       const uint64_t want = has_prev ? ((uint64_t)(uint32_t)(c + 1) | ((uint64_t)(uint32_t)(c + 1) << 32))
                                      : (uint64_t)(uint32_t)(c + 1);
       const uint64_t mask = has_prev ? ~0ull : 0xffffffffull;
-      while ((fl & mask) != want) {
-        __builtin_amdgcn_s_sleep(1);
-        fl = lds_peek_pair(&s_flag[sl][0]);
+      if ((fl & mask) != want) {
+        fl = lds_peek_pair(&s_flag[sl][0]);   // the read-ahead may predate the flags
+        while ((fl & mask) != want) {
+          __builtin_amdgcn_s_sleep(1);
+          fl = lds_peek_pair(&s_flag[sl][0]);
+        }
       }
       lds_acquire();
-      fl = lds_peek_pair(&s_flag[(c + 1) % NC][0]);   // next chunk's flags, read ahead
       int st = lds_peek(&s_stored);
       // the whole chunk's inputs into registers first, so that LDS latency is
       // paid once per chunk and not inside the dependent chain
@@ -440,6 +739,7 @@ __global__ __launch_bounds__(512) void k_sweep_ws(SweepParams p) {
         res[w] = v;
         west = v;
       }
+      fl = lds_peek_pair(&s_flag[(c + 1) % NC][0]);   // next chunk's flags, read ahead
       while (st < c - 1) {   // output buffer c & 1 is free
         __builtin_amdgcn_s_sleep(1);
         st = lds_peek(&s_stored);
@@ -619,14 +919,16 @@ hipError_t launch_ilu0(const Dia &A, const BatchGeom &g, Factors64 f64, Factors3
 template <int OP, int PREC, bool TAB>
 static hipError_t launch_sweep_t(const SweepParams &p, hipStream_t s) {
   constexpr bool CAN_CMP = OP == 0 || TAB;   // three arrays per tile
+  const int grid = p.g.xcd_group > 0 ? 8 * p.g.xcd_group : p.g.nstrips;
   switch (p.g.rows) {
-    case 15: hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC, TAB, false>), dim3(p.g.nstrips), dim3(512), 0, s, p); break;
+    case 15: hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC, TAB, false>), dim3(p.g.nstrips), dim3(ADR_SWEEP_THREADS), 0, s, p); break;
     case 31:
       if (CAN_CMP && p.g.compact)
-        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, CAN_CMP>), dim3(p.g.nstrips), dim3(512), 0, s, p);
+        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, CAN_CMP>), dim3(p.g.nstrips), dim3(ADR_SWEEP_THREADS), 0, s, p);
       else
-        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, false>), dim3(p.g.nstrips), dim3(512), 0, s, p);
+        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, false>), dim3(grid), dim3(ADR_SWEEP_THREADS), 0, s, p);
       break;
+
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
