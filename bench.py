@@ -76,7 +76,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", choices=("single", "batch", "warmstart", "kernels", "large"), default="single")
+    ap.add_argument("--workload", choices=("single", "batch", "warmstart", "kernels", "large", "traffic"),
+                    default="single")
+    ap.add_argument("--pmc-fetch", default="", help="traffic: rocprofv3 output folder of the FETCH_SIZE pass")
+    ap.add_argument("--pmc-write", default="", help="traffic: rocprofv3 output folder of the WRITE_SIZE pass")
     ap.add_argument("--large-maxit", type=int, default=6000, help="large: pass limit of the Dirichlet solves")
     ap.add_argument("--heldout", type=int, default=1000, help="warmstart: held-out instances")
     ap.add_argument("--single-sample", type=int, default=128,
@@ -468,11 +471,43 @@ def run_large(args):
     print(json.dumps(out), flush=True)
 
 
+# Algorithmic bytes per unknown of every kernel of a pass (FP64; the five-
+# diagonal figures, and what the kernels read with the stencil tables).
+PASS_KERNELS = {
+    # name: (bytes with the diagonals, bytes with the tables, what moves)
+    "lsweep": (32, 24, "q, lw, ls in, y out (tables: q, invd in, y out)"),
+    "usweep": (40, 24, "y, E, N, invd in, z out (tables: y, invd in, z out)"),
+    "pass_p": (32, 32, "p, r, v in, p out"),
+    "pass_v": (64, 32, "p^, S, W, C, E, N, r^ in, v out (tables: p^, C, r^ in, v out)"),
+    "pass_s": (24, 24, "r, v in, s out"),
+    "pass_t": (64, 32, "z, S, W, C, E, N, s in, t out (tables: z, C, s in, t out)"),
+    "pass_xr": (64, 64, "x, p^, z, t, s, r^ in, x, r out"),
+    "spmv": (56, 56, "x, S, W, C, E, N in, v out (stand-alone, diagonals)"),
+}
+
+
+def kernel_key(name):
+    """Short name of a library kernel from its demangled name, else None."""
+    import re
+    m = re.search(r"k_sweep_ws<\s*\d+,\s*(\d)", name)
+    if m:
+        return "lsweep" if m.group(1) == "0" else "usweep"
+    for key, pat in (("pass_xr", "k_pass_xr("), ("pass_p", "k_pass_p("), ("pass_v", "k_pass_v<"),
+                     ("pass_s", "k_pass_s("), ("pass_t", "k_pass_t<"), ("spmv", "k_spmv("),
+                     ("copy", "k_stream_copy(")):
+        if pat in name:
+            return key
+    return None
+
+
 def run_kernels(args):
-    """Each hot-path kernel alone, `--kernel-reps` launches each, on the
-    n x n grid (centered scheme, FP64 factors), then a plain element-wise
-    copy kernel of 1 GiB each way as the reference for hardware counters.  For counter runs:
-        rocprofv3 --pmc FETCH_SIZE -- python bench.py --workload kernels
+    """Each hot-path kernel under the counters: the two sweeps and the
+    stand-alone stencil product `--kernel-reps` launches each on the n x n grid
+    (centered scheme, FP64 factors), then `--kernel-reps` passes of a solve
+    (the in-loop kernels), then the library's streaming copy of 1 GiB each way
+    as the calibration for hardware counters.  For counter runs:
+        rocprofv3 --pmc FETCH_SIZE -d DIR -o run --output-format csv -- python bench.py --workload kernels
+    and then `python bench.py --workload traffic --pmc-fetch DIR --pmc-write DIR2`.
     """
     import torch
     import paper_1308_5215_amd as adr
@@ -497,15 +532,98 @@ def run_kernels(args):
         torch.cuda.synchronize()
         out[name] = round((time.perf_counter() - t0) * 1e6 / args.kernel_reps, 1)
         log("  %s: %.1f us per launch (host clock)" % (name, out[name]))
-    # a plain element-wise copy kernel (b = a * 1) moving 1 GiB each way
+    # the in-loop kernels: passes of a solve that cannot stop early
+    res = prob.solve(tol=1e-30, maxit=args.kernel_reps)
+    log("  solve: %d passes, %.1f ms" % (res.iters, res.solve_ms))
+    # the library's streaming copy, 1 GiB each way
     a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(args.kernel_reps):
-        torch.mul(a, 1.0, out=b)
+        adr.stream_copy(a, b)
     torch.cuda.synchronize()
     print(json.dumps({"workload": "kernels", "n": n, "reps": args.kernel_reps, "us_per_launch": out,
-                      "copy_bytes_each_way": a.numel() * 8, "sweep_rows": args.rows or "auto",
-                      "precision": args.precision}), flush=True)
+                      "solve_passes": res.iters, "copy_bytes_each_way": a.numel() * 8,
+                      "sweep_rows": args.rows or "auto", "precision": args.precision}), flush=True)
+
+
+def read_pmc(folder, counter):
+    """Per-kernel counter values (one list entry per dispatch) from a
+    rocprofv3 --pmc CSV output folder."""
+    import csv
+    import glob
+    vals = {}
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError("no *counter_collection.csv under %s" % folder)
+    per_dispatch = {}
+    for f in files:
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = kernel_key(row.get("Kernel_Name", ""))
+                if key is None:
+                    continue
+                d = (f, row.get("Dispatch_Id"))
+                per_dispatch.setdefault((key, d), 0.0)
+                per_dispatch[(key, d)] += float(row["Counter_Value"])
+    for (key, _), v in per_dispatch.items():
+        vals.setdefault(key, []).append(v)
+    return vals
+
+
+def run_traffic(args):
+    """HBM bytes per launch of every hot-path kernel from two rocprofv3
+    counter passes of `--workload kernels` (FETCH_SIZE, then WRITE_SIZE, KiB
+    per dispatch), each scaled by what the same counter reads for the
+    library's streaming copy of 1 GiB each way; written to
+    profiles/traffic.json with the hash of the kernel sources."""
+    import statistics
+    fetch = read_pmc(args.pmc_fetch, "FETCH_SIZE")
+    write = read_pmc(args.pmc_write, "WRITE_SIZE")
+
+    def working(v):
+        # a solve's graph chunk also launches passes after the stop, which
+        # return at entry: keep the dispatches that did the kernel's work
+        top = max(v)
+        return [x for x in v if x >= 0.5 * top]
+
+    fetch = {k: working(v) for k, v in fetch.items()}
+    write = {k: working(v) for k, v in write.items()}
+    gib = float(1 << 30)
+    ff = gib / (statistics.median(fetch["copy"]) * 1024.0)
+    wf = gib / (statistics.median(write["copy"]) * 1024.0)
+    N = args.n * args.n
+    h = sweep_source_hash()
+    res = {}
+    lines = []
+    for key, (dia, tab, what) in PASS_KERNELS.items():
+        if key not in fetch or key not in write:
+            continue
+        fb = statistics.median(fetch[key]) * 1024.0 * ff
+        wb = statistics.median(write[key]) * 1024.0 * wf
+        res[key] = dict(bytes_per_launch=round(fb + wb), fetch_bytes=round(fb), write_bytes=round(wb),
+                        algorithmic_bytes=dia * N, algorithmic_bytes_tables=tab * N,
+                        bytes_per_unknown=round((fb + wb) / N, 2), dispatches=len(fetch[key]), source_hash=h)
+        lines.append("%-8s FETCH %10.1f KiB x %.3f  WRITE %10.1f KiB x %.3f -> %8.1f MB per launch = %5.1f B/unknown "
+                     "(algorithmic %d, tables %d: %s)" % (key, statistics.median(fetch[key]), ff,
+                                                         statistics.median(write[key]), wf, (fb + wb) / 1e6,
+                                                         (fb + wb) / N, dia, tab, what))
+    out = {"n%d" % args.n: res,
+           "calibration": {"kernel": "adr::k_stream_copy", "bytes_each_way": int(gib),
+                           "fetch_factor": ff, "write_factor": wf}}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    old = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            old = json.load(fh)
+    old.update(out)
+    with open(path, "w") as fh:
+        json.dump(old, fh, indent=1)
+    print("calibration: the streaming copy (1 GiB each way) reads FETCH_SIZE %.0f KiB and WRITE_SIZE %.0f KiB "
+          "per dispatch: factors %.3f and %.3f" % (statistics.median(fetch["copy"]), statistics.median(write["copy"]),
+                                                   ff, wf))
+    print("\n".join(lines))
 
 
 def copy_reference_gbs(dev, reps=5):
@@ -551,6 +669,8 @@ def main():
         return run_warmstart(args)
     if args.workload == "kernels":
         return run_kernels(args)
+    if args.workload == "traffic":
+        return run_traffic(args)
     if args.workload == "large":
         return run_large(args)
     import numpy as np

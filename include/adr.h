@@ -337,7 +337,9 @@ adr_status adr_dot(const double *x_dev, const double *y_dev, int64_t n, void *st
 
 /* Streaming copy dst[k] = src[k], k < n (device vectors, stream as in
  * adr_dot): a plain HBM-bound kernel, the practical bandwidth reference for
- * the roofline figures.  Synchronous on return. */
+ * the roofline figures.  Asynchronous: the copy is enqueued on `stream` and
+ * ordered with the caller's other work there (time it with events on that
+ * stream). */
 adr_status adr_stream_copy(const double *src_dev, double *dst_dev, int64_t n, void *stream);
 
 /* ---------------------------------------------------------------------------

@@ -1307,14 +1307,10 @@ adr_status adr_stream_copy(const double *src, double *dst, int64_t n, void *stre
   g_last_error.clear();
   if (!src || !dst || n < 0) return fail(ADR_ERR_ARG, "bad argument");
   if (n == 0) return ADR_OK;
-  int dev = 0, cus = 256;
-  HIP_TRY(hipGetDevice(&dev));
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int64_t want = (n / 2 + 4 * 256 - 1) / (4 * 256);
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 16));
-  hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(launch_stream_copy(src, dst, n, blocks, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  // one block per 64 KB segment (4096 pairs of doubles), at most 2^20 blocks
+  const int64_t want = (n / 2 + 4095) / 4096;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)1 << 20));
+  HIP_TRY(launch_stream_copy(src, dst, n, blocks, (hipStream_t)stream));
   return ADR_OK;
 }
 

@@ -748,25 +748,35 @@ hipError_t launch_max_error(const MaxErrArgs &a, const Stream1D &g, hipStream_t 
 
 // Streaming copy: each thread moves 16-byte words, four loads in flight
 // before the four stores, grid-stride over the array.
-__global__ __launch_bounds__(BLK) void k_stream_copy(const double2 *__restrict__ src, double2 *__restrict__ dst,
-                                                     int64_t n2) {
-  const int64_t stride = (int64_t)gridDim.x * BLK;
-  int64_t k = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  for (; k + 3 * stride < n2; k += 4 * stride) {
-    const double2 a0 = src[k], a1 = src[k + stride], a2 = src[k + 2 * stride], a3 = src[k + 3 * stride];
-    dst[k] = a0;
-    dst[k + stride] = a1;
-    dst[k + 2 * stride] = a2;
-    dst[k + 3 * stride] = a3;
+// Each block copies one contiguous segment of `per` 16-byte elements, four
+// loads in flight per thread, with non-temporal hints (the data is not
+// reused): measured the fastest copy form on MI355X (5.7 TB/s for 1 GiB each
+// way, against 4.2-4.6 TB/s for a grid-stride loop).
+typedef double copy_v2 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(BLK) void k_stream_copy(const copy_v2 *__restrict__ src, copy_v2 *__restrict__ dst,
+                                                     int64_t n2, int64_t per) {
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(b0 + per, n2);
+  constexpr int U = 4;
+  for (int64_t k = b0 + threadIdx.x; k < b1; k += U * BLK) {
+    copy_v2 a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k + u * BLK < b1) a[u] = __builtin_nontemporal_load(&src[k + u * BLK]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k + u * BLK < b1) __builtin_nontemporal_store(a[u], &dst[k + u * BLK]);
   }
-  for (; k < n2; k += stride) dst[k] = src[k];
 }
 __global__ void k_copy_tail(const double *src, double *dst, int64_t n) {
   if (threadIdx.x == 0 && (n & 1)) dst[n - 1] = src[n - 1];
 }
 hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(BLK), 0, s, (const double2 *)src, (double2 *)dst, n / 2);
-  hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, src, dst, n);
+  const int64_t n2 = n / 2;
+  if (n2 > 0) {
+    const int64_t per = (n2 + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(BLK), 0, s, (const copy_v2 *)src, (copy_v2 *)dst, n2, per);
+  }
+  if (n & 1) hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, src, dst, n);
   return hipGetLastError();
 }
 
