@@ -145,6 +145,7 @@ struct adr_problem {
   std::vector<int> nx, ny, scheme, bc;
   std::vector<Inst> inst;      // host copy of the instance table
   Inst *d_inst = nullptr;
+  int *d_sorder = nullptr;   // instances in strip-ticket order
   int64_t ntot = 0;            // unknowns over the batch
   int nblk = 0, nstrips = 0, rows = 0, max_ny = 0;
   int compact = -1;            // 31-row sweep ring: -1 automatic, 0 deep, 1 compact
@@ -213,7 +214,9 @@ struct adr_problem {
     return (nstrips + 7) / 8;
 #endif
   }
-  BatchGeom geom() const { return BatchGeom{d_inst, count, nblk, nstrips, rows, ring_compact(), xcd_group()}; }
+  BatchGeom geom() const {
+    return BatchGeom{d_inst, count, nblk, nstrips, rows, ring_compact(), xcd_group(), d_sorder};
+  }
 };
 
 namespace {
@@ -268,7 +271,6 @@ adr_status build_table(adr_problem *P, int R) {
     I.off = off;
     I.blk0 = blk;
     I.nblk = (nb + 7) & ~7;   // whole XCD rounds: a block's XCD is its local index mod 8
-    I.strip0 = strip;
     I.nstrips = (I.ny + R - 1) / R;
     I.ho_off = ho;
     I.fd = make_fastdiv((uint32_t)I.nx);
@@ -280,13 +282,33 @@ adr_status build_table(adr_problem *P, int R) {
     strip += I.nstrips;
     ho += (int64_t)I.nstrips * I.nx;
   }
+  // Strip tickets go to the instances largest first (strips times chunks per
+  // strip; ties in batch order), so that the long instances start early and
+  // the short ones fill the tail (measured 8 % faster on a batch of 256
+  // instances of 128^2..1024^2 than the batch order).  Strips of one
+  // instance keep consecutive tickets.
+  std::vector<int> ord(P->count);
+  for (int k = 0; k < P->count; ++k) ord[k] = k;
+  auto work = [&](int k) {
+    const Inst &I = P->inst[k];
+    return (int64_t)I.nstrips * ((I.nx + R + 15) / 16);
+  };
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
+  int s0 = 0;
+  for (int k : ord) {
+    P->inst[k].strip0 = s0;
+    s0 += P->inst[k].nstrips;
+  }
   P->ntot = off;
   P->tab_len = tabo;
   P->nblk = blk;
   P->nstrips = strip;
   P->rows = R;
   if (!P->d_inst) HIP_TRY(dalloc(&P->d_inst, (size_t)P->count, P->bytes));
+  if (!P->d_sorder) HIP_TRY(dalloc(&P->d_sorder, (size_t)P->count, P->bytes));
   HIP_TRY(hipMemcpyAsync(P->d_inst, P->inst.data(), sizeof(Inst) * (size_t)P->count, hipMemcpyHostToDevice,
+                         P->stream));
+  HIP_TRY(hipMemcpyAsync(P->d_sorder, ord.data(), sizeof(int) * (size_t)P->count, hipMemcpyHostToDevice,
                          P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   return ADR_OK;
@@ -607,6 +629,7 @@ void adr_destroy(adr_problem *P) {
   pfree(P, P->handoff);
   pfree(P, P->err);
   dfree(P->d_inst);
+  dfree(P->d_sorder);
   dfree(P->d_feat);
   dfree(P->tab_bad);
   if (P->h_st) (void)hipHostFree(P->h_st);

@@ -57,7 +57,7 @@ struct Inst {
   int32_t chunk;            // points per streaming block (multiple of 1024)
   int64_t off;              // offset of the instance in every batched vector
   int32_t blk0, nblk;       // streaming blocks (blk0 and nblk multiples of 8)
-  int32_t strip0, nstrips;  // wavefront strips (for the batch's strip height)
+  int32_t strip0, nstrips;  // wavefront strips (for the batch's strip height), numbered in ticket order
   int64_t ho_off;           // offset in the hand-off buffer (64-bit words)
   FastDiv fd;               // division by nx
   int32_t pad;
@@ -84,6 +84,7 @@ struct BatchGeom {
   int rows;           // strip height R
   int compact;        // 31-row sweeps: 76 KB ring, two workgroups per CU (see adr_sweeps.hip)
   int xcd_group;      // > 0: strips by workgroup index, xcd_group consecutive strips per XCD
+  const int *sorder;  // device: instances in strip-ticket order (largest work first); strip0 ascends along it
 };
 
 // Single-instance streaming geometry (assembly, diagnostics).

@@ -130,15 +130,17 @@ __device__ __forceinline__ Pair<T> swap_pair(Pair<T> r) {
   return Pair<T>{r.y, r.x};
 }
 
-// Instance owning global strip t (instances sorted by strip0).
-__device__ __forceinline__ int find_strip_inst(const Inst *inst, int ninst, int t) {
+// Instance owning strip ticket t: strips are numbered along the ticket order
+// of the instances (ord, largest work first; null: table order), so strip0
+// ascends along ord and a binary search over it finds the owner.
+__device__ __forceinline__ int find_strip_inst(const Inst *inst, const int *ord, int ninst, int t) {
   int lo = 0, hi = ninst - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (inst[mid].strip0 <= t) lo = mid;
+    if (inst[ord ? ord[mid] : mid].strip0 <= t) lo = mid;
     else hi = mid - 1;
   }
-  return lo;
+  return ord ? ord[lo] : lo;
 }
 
 __device__ __forceinline__ void strip_finish(const SweepSync &sy, int nstrips) {
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(ADR_SWEEP_THREADS) void k_sweep_ws(SweepParams p) {
     }
   } else if (tid == 0) {
     const int t = (int)atomicAdd(&p.sync.ticket[0], 1u);
-    const int ii = find_strip_inst(p.g.inst, p.g.ninst, t);
+    const int ii = find_strip_inst(p.g.inst, p.g.sorder, p.g.ninst, t);
     s_inst = ii;
     s_strip = t - p.g.inst[ii].strip0;
     s_computed = 0;
@@ -788,7 +790,7 @@ __global__ __launch_bounds__(64) void k_ilu0(FactorParams p) {
   unsigned tk = 0;
   if (lane == 0) tk = atomicAdd(&p.sync.ticket[0], 1u);
   const int t = __builtin_amdgcn_readfirstlane((int)tk);
-  const int ii = find_strip_inst(p.g.inst, p.g.ninst, t);
+  const int ii = find_strip_inst(p.g.inst, p.g.sorder, p.g.ninst, t);
   const Inst I = p.g.inst[ii];
   const int strip = t - I.strip0;
   const int nx = I.nx, ny = I.ny;
