@@ -307,7 +307,8 @@ def run_batch(args):
 def run_warmstart(args):
     """Learned initial guess: held-out 256 x 256 instances (seeds 100000...,
     eps log-uniform in [1e-3, 1], X, Y in [0.5, 2], Dirichlet or Neumann outer
-    sides, manufactured f + Gaussian random field) solved to relative residual
+    sides, upwind or centered convection, manufactured f + Gaussian random
+    field) solved to relative residual
     1e-10 from the zero guess and from the trained network's guess (committed
     weights; the guess time counts against it).  FP64 throughout."""
     import numpy as np
@@ -333,7 +334,7 @@ def run_warmstart(args):
     H = n + 2
     B = 64
     xin = torch.zeros((B, H, H, 32), dtype=torch.bfloat16, device="cuda")
-    xin[..., :9] = torch.randn((B, H, H, 9), device="cuda").to(torch.bfloat16)
+    xin[..., :10] = torch.randn((B, H, H, 10), device="cuda").to(torch.bfloat16)
     u = torch.empty((B, H, H), dtype=torch.float32, device="cuda")
     tgt = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
     fwd_flop = 2.0 * B * H * H * 9 * 32 * (5 * 32 + 16)
@@ -370,9 +371,11 @@ def run_warmstart(args):
         "ms_per_step": round(wall * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "learned warm start, %d held-out instances 256x256 (seeds %d..), eps log-uniform "
-                               "[1e-3,1], X,Y in [0.5,2], Dirichlet/Neumann p=1/2, upwind, manufactured f + GRF "
-                               "(length 0.1, amp 0.1 max|f|)" % (len(seeds), seeds[0]),
-                   "network": "6 x conv3x3, 9->32->...->32->1, GELU, bf16 weights, fp32 accumulate",
+                               "[1e-3,1], X,Y in [0.5,2], Dirichlet/Neumann p=1/2, upwind/centered p=1/2, "
+                               "manufactured f + GRF (length 0.1, amp 0.1 max|f|)" % (len(seeds), seeds[0]),
+                   "network": "6 x conv3x3, 10->32->...->32->1, GELU, bf16 weights, fp32 accumulate",
+                   "well_posed": "instance classifier: expected to converge, Neumann g_y <= %g, wrong-sign "
+                                 "couplings only with cell Peclet <= %g" % (tw.G_Y_MAX, tw.PE_MAX),
                    "weights": os.path.relpath(tw.DEFAULT_WEIGHTS, ROOT), "tol": args.tol},
         "zero_guess_s": round(s["single_zero_ms"] / k / 1e3, 5),
         "summary": s,

@@ -9,7 +9,7 @@
  * the zero guess (||b - A x0||_2 >= ||b||_2) is replaced by zero.
  *
  * Network (fixed architecture): six 3x3 convolutions with zero padding,
- * channels 9 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, exact GELU
+ * channels 10 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, exact GELU
  * (x * Phi(x)) after the first five.  Weights and the activations between
  * layers are stored in bfloat16 (round to nearest even); products are
  * accumulated in FP32.  The pre-activations of the hidden layers are kept in
@@ -22,7 +22,7 @@
  * Tensors are channels-last ("NHWC"): element (b, row, col, c) of a
  * [B][H][W][C] tensor is at ((b*H + row)*W + col)*C + c; row is the y index
  * and col the x index of the node, both counted from the boundary ring.
- * Network inputs always have 32 channels in memory, of which the first nine
+ * Network inputs always have 32 channels in memory, of which the first ten
  * are the fields below and the rest are zero.
  *
  * Input fields of node (I, J), x = I*dx, y = J*dy, I, J in [0, n+1]:
@@ -36,11 +36,12 @@
  *   5, 6: x/X, y/Y;  7, 8: X/2, Y/2 (the node's place in its domain: six
  *      layers of 3x3 convolutions see 13 x 13 nodes, far too few to locate a
  *      node of a large grid from the other fields)
+ *   9: the scheme of the convection term: 0 upwind, 1 centered (Section 4)
  *
  * Parameters are exchanged as one packed FP32 vector: for each layer in
  * order, its weights W[ky][kx][ci][co] (cross-correlation: output at node
  * (row, col) reads input (row + ky - 1, col + kx - 1)) followed by its biases
- * b[co].  adr_cnn_param_count() gives the length (39905).
+ * b[co].  adr_cnn_param_count() gives the length (40193).
  *
  * All device pointers are plain HIP device memory owned by the caller; all
  * calls are synchronous on the network's stream on return.  Errors: as in

@@ -23,7 +23,7 @@ from scipy.special import erf
 
 from . import core
 
-NFIELD = 9
+NFIELD = 10
 CIN = (NFIELD, 32, 32, 32, 32, 32)
 COUT = (32, 32, 32, 32, 32, 1)
 NLAYER = 6
@@ -166,10 +166,11 @@ class Adam:
         return self.p
 
 
-def features(eps, X, Y, nx, ny, bc, field=None, amp=0.0):
-    """The input fields on the (ny+2) x (nx+2) node grid, [ny+2, nx+2, 9]:
+def features(eps, X, Y, nx, ny, bc, field=None, amp=0.0, scheme=0):
+    """The input fields on the (ny+2) x (nx+2) node grid, [ny+2, nx+2, 10]:
     a/5, b/2, (interior) f/10 or (ring) the boundary datum, log10(eps)/3, the
-    ring mask (+1 Dirichlet, -1 Neumann, 0 interior), x/X, y/Y, X/2 and Y/2.
+    ring mask (+1 Dirichlet, -1 Neumann, 0 interior), x/X, y/Y, X/2, Y/2 and
+    the scheme (0 upwind, 1 centered).
     f is the forcing the solver is assembled with:
     f_man + amp max|f_man| field."""
     H, W = ny + 2, nx + 2
@@ -190,6 +191,7 @@ def features(eps, X, Y, nx, ny, bc, field=None, amp=0.0):
             out[J, I, 6] = y / Y
             out[J, I, 7] = X / 2.0
             out[J, I, 8] = Y / 2.0
+            out[J, I, 9] = float(scheme)
             if 1 <= I <= nx and 1 <= J <= ny:
                 out[J, I, 2] = f[J - 1, I - 1] / 10.0
                 continue

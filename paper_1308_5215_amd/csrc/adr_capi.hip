@@ -573,7 +573,7 @@ adr_status ensure_feat_table(adr_problem *P) {
     fi[k].nx = P->nx[k];
     fi[k].ny = P->ny[k];
     fi[k].bc = P->bc[k];
-    fi[k].pad = 0;
+    fi[k].scheme = P->scheme[k];
     fi[k].off = P->inst[k].off;
   }
   size_t b = 0;

@@ -35,7 +35,7 @@ constexpr int CH = 32;        // channels of every stored activation tensor
 constexpr int TS = 16;        // output tile edge (nodes)
 constexpr int HALO = TS + 2;  // staged input tile edge
 constexpr int NLAYER = 6;
-constexpr int NFIELD = 9;    // input fields per node
+constexpr int NFIELD = 10;   // input fields per node
 constexpr int CIN[NLAYER] = {NFIELD, 32, 32, 32, 32, 32};
 constexpr int COUT[NLAYER] = {32, 32, 32, 32, 32, 1};
 constexpr int WGRAD_MAX_WG = 512;
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(256) void k_features(const FeatInst *fi, int count,
   u32x4 *o = (u32x4 *)(out + k * CH);
   o[0] = u32x4{pack2((float)(av / 5.0), (float)(bv / 2.0)), pack2((float)fv, (float)(log10(P.eps) / 3.0)),
                pack2((float)mask, (float)(x / P.X)), pack2((float)(y / P.Y), (float)(P.X / 2.0))};
-  o[1] = u32x4{pack2((float)(P.Y / 2.0), 0.f), 0u, 0u, 0u};
+  o[1] = u32x4{pack2((float)(P.Y / 2.0), (float)P.scheme), 0u, 0u, 0u};
   o[2] = u32x4{0u, 0u, 0u, 0u};
   o[3] = u32x4{0u, 0u, 0u, 0u};
 }

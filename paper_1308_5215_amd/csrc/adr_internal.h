@@ -197,7 +197,7 @@ void clear_error();
 // ---- warm-start network (adr_cnn.hip) ----
 struct FeatInst {
   double eps, X, Y;
-  int32_t nx, ny, bc, pad;
+  int32_t nx, ny, bc, scheme;   // scheme: 0 upwind, 1 centered
   int64_t off;          // offset of the instance in the batched vectors
 };
 hipError_t launch_cnn_features(const FeatInst *fi_dev, int count, int H, int W, const double *F,

@@ -5,25 +5,27 @@ import numpy as np
 from .fields import _rng
 
 # layer channels of the warm-start network (input fields -> u)
-CIN = (9, 32, 32, 32, 32, 32)
+CIN = (10, 32, 32, 32, 32, 32)
 COUT = (32, 32, 32, 32, 32, 1)
 
 
-def warmstart_instance(seed, n=256, scheme=0):
+def warmstart_instance(seed, n=256, scheme=None):
     """One instance for seed `seed`: n x n interior grid, eps log-uniform in
     [1e-3, 1], X and Y uniform in [0.5, 2], boundary type (0 Dirichlet,
-    1 Neumann on x = X and y = Y) with p = 1/2, the given scheme, and the seed
-    of its random forcing field."""
+    1 Neumann on x = X and y = Y) with p = 1/2, the scheme (0 upwind,
+    1 centered; drawn with p = 1/2 from a stream of its own unless given),
+    and the seed of its random forcing field."""
     r = _rng(0x57A27, seed)
-    return dict(
+    d = dict(
         n=int(n),
         eps=float(10.0 ** r.uniform(-3.0, 0.0)),
         X=float(r.uniform(0.5, 2.0)),
         Y=float(r.uniform(0.5, 2.0)),
-        scheme=int(scheme),
         bc=int(r.integers(0, 2)),
         field_seed=int(r.integers(0, 2 ** 31 - 1)),
     )
+    d["scheme"] = int(_rng(0x5C4E3E, seed).integers(0, 2)) if scheme is None else int(scheme)
+    return d
 
 
 def initial_params(seed=0):

@@ -12,7 +12,7 @@ from synthetic import warmstart as ws
 
 
 def test_param_count_and_layout():
-    assert cnn.param_count() == 39905
+    assert cnn.param_count() == 40193
     p = np.arange(cnn.param_count(), dtype=np.float64)
     layers = cnn.unpack(p)
     assert [w.shape for w, _ in layers] == [(3, 3, ci, co) for ci, co in zip(cnn.CIN, cnn.COUT)]
@@ -160,7 +160,7 @@ def test_features_pinned_to_exact_solution_and_forcing(bc):
             assert math.isclose(f[J, I, 0], (1 + x * x) / 5, rel_tol=1e-15)
             assert math.isclose(f[J, I, 1], X * math.exp(-y) / 2, rel_tol=1e-15)
             assert math.isclose(f[J, I, 5], x / X, rel_tol=1e-15) and math.isclose(f[J, I, 6], y / Y, rel_tol=1e-15)
-            assert f[J, I, 7] == X / 2 and f[J, I, 8] == Y / 2
+            assert f[J, I, 7] == X / 2 and f[J, I, 8] == Y / 2 and f[J, I, 9] == 0.0
             ring = not (1 <= I <= nx and 1 <= J <= ny)
             if not ring:
                 assert f[J, I, 4] == 0.0
@@ -180,6 +180,15 @@ def test_features_pinned_to_exact_solution_and_forcing(bc):
             else:                  # normal derivative on y = Y
                 d = (core.u_exact(x, Y + h, X, Y) - core.u_exact(x, Y - h, X, Y)) / (2 * h)
                 assert math.isclose(f[J, I, 2], d, rel_tol=1e-7, abs_tol=1e-9)
+
+
+def test_scheme_field_marks_the_centered_scheme_only():
+    eps, X, Y, nx, ny = 0.05, 1.3, 0.7, 9, 6
+    f0 = cnn.features(eps, X, Y, nx, ny, core.DIRICHLET)
+    f1 = cnn.features(eps, X, Y, nx, ny, core.DIRICHLET, scheme=core.CENTERED)
+    assert core.CENTERED == 1 and core.UPWIND == 0
+    assert np.all(f0[..., 9] == 0.0) and np.all(f1[..., 9] == 1.0)
+    assert np.array_equal(f0[..., :9], f1[..., :9])
 
 
 def test_features_with_field_use_the_assembled_forcing():

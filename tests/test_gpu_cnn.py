@@ -49,6 +49,14 @@ def _net(H, W, B):
     return adr.WarmStartNet(H, W, B)
 
 
+# The reference rounds every stored activation to bfloat16 at the same points
+# as the kernels but sums in FP64 where they sum in FP32, so now and then a
+# pre-activation lands on the other side of a bfloat16 rounding boundary and
+# one activation moves by one bfloat16 ulp (2^-8 relative); over the output
+# such flips stay below half an ulp in the relative L2 norm.
+U_TOL = 2.0 ** -9
+
+
 def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
@@ -63,7 +71,7 @@ def test_forward_matches_reference(B, H, W):
     u = net.forward(xd).cpu().numpy()
     ref, _ = ocnn.forward(p.astype(np.float64), x, emulate=True)
     assert u.shape == ref.shape
-    assert _rel(u, ref) <= 1e-3, _rel(u, ref)
+    assert _rel(u, ref) <= U_TOL, _rel(u, ref)
     assert np.max(np.abs(u - ref)) <= 2e-2 * np.max(np.abs(ref))
     # the reference without bfloat16 rounding is measurably further away
     raw, _ = ocnn.forward(p.astype(np.float64), x, emulate=False)
@@ -82,7 +90,7 @@ def test_gradient_matches_reference(B, H, W):
     loss, g, u = net.gradient(xd, torch.from_numpy(t).cuda(), want_u=True)
     rl, rg, ru = ocnn.loss_and_grad(p.astype(np.float64), x, t.astype(np.float64), emulate=True)
     assert abs(loss - rl) <= 1e-4 * rl
-    assert _rel(u.cpu().numpy(), ru) <= 1e-3
+    assert _rel(u.cpu().numpy(), ru) <= U_TOL
     off = 0
     for l, (ci, co) in enumerate(zip(ocnn.CIN, ocnn.COUT)):
         nw = 9 * ci * co
@@ -168,15 +176,17 @@ def test_features_match_reference(bc):
               for d in inst]
     fd = torch.from_numpy(np.concatenate(fields)).cuda()
     bcs = [bc] * count
+    schemes = ["upwind", "centered", "upwind"][:count]
     batch = adr.assemble_batch([d["eps"] for d in inst], [d["X"] for d in inst], [d["Y"] for d in inst],
-                               [n] * count, [n] * count, ["upwind"] * count, bcs, field=fd, amp=0.1)
+                               [n] * count, [n] * count, schemes, bcs, field=fd, amp=0.1)
     got = batch.features().float().cpu().numpy().astype(np.float64)
     assert got.shape == (count, n + 2, n + 2, 32)
     nf = ocnn.NFIELD
     assert np.all(got[..., nf:] == 0)
     b = core.DIRICHLET if bc == "dirichlet" else core.NEUMANN
     for k, d in enumerate(inst):
-        ref = ocnn.bf16(ocnn.features(d["eps"], d["X"], d["Y"], n, n, b, field=fields[k], amp=0.1))
+        sc = core.CENTERED if schemes[k] == "centered" else core.UPWIND
+        ref = ocnn.bf16(ocnn.features(d["eps"], d["X"], d["Y"], n, n, b, field=fields[k], amp=0.1, scheme=sc))
         # device and host exponentials may differ in the last bit: one bfloat16 step at most
         assert np.all(np.abs(got[k, ..., :nf] - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-30)
         assert np.mean(got[k, ..., :nf] == ref) > 0.99

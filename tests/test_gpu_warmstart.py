@@ -16,7 +16,6 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 WEIGHTS = os.path.join(ROOT, "paper_1308_5215_amd", "weights", "warmstart_256.npy")
 N = 256
 HELDOUT = list(range(100000, 100020))
-U_MAX = 2.5
 
 
 def _torch():
@@ -58,8 +57,9 @@ def test_trained_network_saves_iterations_on_held_out_instances():
     z = batch.solve(tol=1e-10, maxit=1500)
     x0, used = batch.warm_start(net)
     w = batch.solve(tol=1e-10, maxit=1500, x0=x0)
-    umax = np.array([float(torch.max(torch.abs(x))) for x in batch.split(z.x)])
-    ok = (z.status == 0) & (w.status == 0) & (umax <= U_MAX)
+    from paper_1308_5215_amd.train_warmstart import well_posed
+    wp = np.array([well_posed(d, 1e-10) for d in inst])
+    ok = (z.status == 0) & (w.status == 0) & wp
     assert ok.sum() >= 12
     ratio = w.iters[ok] / z.iters[ok]
     assert used[ok].mean() >= 0.9
