@@ -14,6 +14,7 @@
 // (channel-major) so that one lane reads 8 consecutive nodes of one channel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -40,6 +41,7 @@ constexpr int CIN[NLAYER] = {NFIELD, 32, 32, 32, 32, 32};
 constexpr int COUT[NLAYER] = {32, 32, 32, 32, 32, 1};
 constexpr int WGRAD_MAX_WG = 512;
 
+
 constexpr int64_t layer_size(int l) { return 9LL * CIN[l] * COUT[l] + COUT[l]; }
 constexpr int64_t param_count() {
   int64_t s = 0;
@@ -56,13 +58,30 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+// two values rounded to nearest even by the hardware conversion
+// (v_cvt_pk_bf16_f32): the same bits as f2bf for every finite value
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
-  return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+  typedef float v2f __attribute__((ext_vector_type(2)));
+  typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
 }
 
-// exact GELU and its derivative
+// GELU z Phi(z) of the forward pass, erf by Abramowitz & Stegun, Handbook of
+// Mathematical Functions, formula 7.1.26 (|error| <= 1.5e-7, far below the
+// bfloat16 step the activations are rounded to; one reciprocal, one
+// exponential, a degree-5 polynomial), written for Phi directly: with
+// a = |z| / sqrt(2), t = 1 / (1 + p a) and h =
+// (q(t) / 2) exp(-z^2 / 2), Phi(z) = 1 - h for z >= 0 and h for z < 0 (the
+// halves folded into the coefficients)
 __device__ __forceinline__ float gelu(float z) {
-  return (0.5f * z) * (1.0f + erff(z * 0.70710678118654752f));
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, fabsf(z), 1.0f));
+  float q = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
+  q = fmaf(q, t, 0.5f * 1.421413741f);
+  q = fmaf(q, t, 0.5f * -0.284496736f);
+  q = fmaf(q, t, 0.5f * 0.254829592f);
+  q *= t;
+  const float h = q * __builtin_amdgcn_exp2f((z * (-0.5f * 1.4426950408889634f)) * z);
+  return z * (z >= 0.0f ? 1.0f - h : h);
 }
 __device__ __forceinline__ float gelu_d(float z) {
   const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
@@ -86,80 +105,154 @@ struct ConvArgs {
   uint16_t *h;           // FWD_GELU: activations; BWD_GELU: input gradient
   const float *zprev;    // BWD_GELU: pre-activations of the layer below
   float *u;              // FWD_OUT: [B][H][W]
-  int H, W, tx, ty;
+  int H, W, tx, ty, nb;
 };
 
-// One 16 x 16 output tile per workgroup; wave w computes tile rows 4w..4w+3.
+// 16 x 16 output tiles; wave w computes tile rows 4w..4w+3.  Persistent: a
+// workgroup loads the layer's weights into registers once and takes tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the input tile two steps ahead is
+// loaded into registers (two sets, alternating) while the current one's
+// products run, and the one a step ahead is written to the other half of a
+// double-buffered LDS tile afterwards.
 template <int NOUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+__global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
   constexpr int PS = 40;  // LDS node stride in bf16 (80 B: rows of 16 B reads do not collide)
   constexpr int MB = NOUT / 16;
-  __shared__ __attribute__((aligned(16))) uint16_t s_in[HALO * HALO * PS];
+  constexpr int NLD = (HALO * HALO * 4 + 255) / 256;   // 16-byte staging loads per thread
+  __shared__ __attribute__((aligned(16))) uint16_t s_in[2][HALO * HALO * PS];
+  // each wave's 4 x 16 output nodes (32 bf16 channels), stored from here with
+  // whole-node 16-byte writes instead of four 8-byte pieces per node
+  constexpr int OPS = CH + 8;   // node stride in bf16 (80 B)
+  __shared__ __attribute__((aligned(16))) uint16_t s_out[4][4 * TS * OPS];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int px = lane & 15, q = lane >> 4;
-  int bid = blockIdx.x;
-  const int tpx = bid % a.tx;
-  bid /= a.tx;
-  const int tpy = bid % a.ty;
-  const int b = bid / a.ty;
-  const int y0 = tpy * TS, x0 = tpx * TS;
-  const uint16_t *inb = a.in + (size_t)b * a.H * a.W * CH;
-  for (int i = tid; i < HALO * HALO * 4; i += 256) {
-    const int c8 = i & 3, node = i >> 2;
-    const int r = node / HALO, c = node - r * HALO;
-    const int gy = y0 + r - 1, gx = x0 + c - 1;
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-      v = *(const u32x4 *)(inb + ((size_t)gy * a.W + gx) * CH + c8 * 8);
-    *(u32x4 *)(s_in + node * PS + c8 * 8) = v;
-  }
+  const int ntiles = a.nb * a.tx * a.ty;
+  int t = blockIdx.x;
+  if (t >= ntiles) return;
+  auto origin = [&](int tile, int &b, int &y0, int &x0) {
+    const int tpx = tile % a.tx, rest = tile / a.tx;
+    const int tpy = rest % a.ty;
+    b = rest / a.ty;
+    y0 = tpy * TS;
+    x0 = tpx * TS;
+  };
+  u32x4 pre0[NLD], pre1[NLD];
+  auto fetch = [&](int tile, u32x4 (&pre)[NLD]) {
+    int b, y0, x0;
+    origin(tile, b, y0, x0);
+    const uint16_t *inb = a.in + (size_t)b * a.H * a.W * CH;
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int i = tid + k * 256;
+      const int c8 = i & 3, node = i >> 2;
+      const int r = node / HALO, c = node - r * HALO;
+      const int gy = y0 + r - 1, gx = x0 + c - 1;
+      pre[k] = u32x4{0u, 0u, 0u, 0u};
+      if (i < HALO * HALO * 4 && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+        pre[k] = *(const u32x4 *)(inb + ((size_t)gy * a.W + gx) * CH + c8 * 8);
+    }
+  };
+  auto put = [&](int buf, const u32x4 (&pre)[NLD]) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int i = tid + k * 256;
+      if (i < HALO * HALO * 4) *(u32x4 *)(&s_in[buf][0] + (i >> 2) * PS + (i & 3) * 8) = pre[k];
+    }
+  };
   v8bf wa[9][MB];
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
+  for (int tp = 0; tp < 9; ++tp)
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
-      wa[t][mb] = as_bf(*(const u32x4 *)(a.w + ((size_t)(t * NOUT + mb * 16 + px)) * CH + q * 8));
-  __syncthreads();
-  v4f acc[4][MB];
+      wa[tp][mb] = as_bf(*(const u32x4 *)(a.w + ((size_t)(tp * NOUT + mb * 16 + px)) * CH + q * 8));
+  v4f acc0[MB];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) acc[r][mb] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = wv * 4 + r;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int dy = t / 3, dx = t % 3;
-      const v8bf bv = as_bf(*(const u32x4 *)(s_in + ((row + dy) * HALO + px + dx) * PS + q * 8));
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) acc[r][mb] = mfma(wa[t][mb], bv, acc[r][mb]);
-    }
+  for (int mb = 0; mb < MB; ++mb) {
+    const int co = mb * 16 + 4 * q;
+    acc0[mb] = MODE == BWD_GELU ? v4f{0.f, 0.f, 0.f, 0.f}
+                                : (MODE == FWD_OUT ? v4f{a.bias[0], 0.f, 0.f, 0.f}
+                                                   : v4f{a.bias[co], a.bias[co + 1], a.bias[co + 2], a.bias[co + 3]});
   }
-  // lane holds channels mb*16 + 4q + i of node (row, px)
+  const int G = gridDim.x;
+  fetch(t, pre0);
+  put(0, pre0);
+  if (t + G < ntiles) fetch(t + G, pre1);
+  // step for tile t from LDS half `buf`: tile t + 2G is fetched into set F
+  // while it runs, then tile t + G (fetched a step earlier into set P) is
+  // put into the other half
+  auto step = [&](int buf, u32x4 (&F)[NLD], const u32x4 (&P)[NLD]) {
+    const int tn = t + G;
+    if (t + 2 * G < ntiles) fetch(t + 2 * G, F);
+    __syncthreads();              // this tile staged; the other half no longer read
+    int b, y0, x0;
+    origin(t, b, y0, x0);
+    const uint16_t *sb = &s_in[buf][0];
+    // forward: the accumulators start at the bias
+    v4f acc[4][MB];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int gy = y0 + wv * 4 + r, gx = x0 + px;
-    if (gy >= a.H || gx >= a.W) continue;
-    const size_t node = ((size_t)b * a.H + gy) * a.W + gx;
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const int co = mb * 16 + 4 * q;
-      const v4f s = acc[r][mb];
-      if (MODE == FWD_GELU) {
-        const float z0 = s[0] + a.bias[co], z1 = s[1] + a.bias[co + 1];
-        const float z2 = s[2] + a.bias[co + 2], z3 = s[3] + a.bias[co + 3];
-        if (a.z) *(v4f *)(a.z + node * CH + co) = v4f{z0, z1, z2, z3};
-        *(u32x2 *)(a.h + node * CH + co) = u32x2{pack2(gelu(z0), gelu(z1)), pack2(gelu(z2), gelu(z3))};
-      } else if (MODE == FWD_OUT) {
-        if (mb == 0 && q == 0) a.u[node] = s[0] + a.bias[0];
-      } else {
-        const v4f zp = *(const v4f *)(a.zprev + node * CH + co);
-        const float g0 = s[0] * gelu_d(zp[0]), g1 = s[1] * gelu_d(zp[1]);
-        const float g2 = s[2] * gelu_d(zp[2]), g3 = s[3] * gelu_d(zp[3]);
-        *(u32x2 *)(a.h + node * CH + co) = u32x2{pack2(g0, g1), pack2(g2, g3)};
+      for (int mb = 0; mb < MB; ++mb) acc[r][mb] = acc0[mb];
+    // taps outside, rows inside: 4 MB independent accumulations in flight
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp) {
+      const int dy = tp / 3, dx = tp % 3;
+      v8bf bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        bv[r] = as_bf(*(const u32x4 *)(sb + ((wv * 4 + r + dy) * HALO + px + dx) * PS + q * 8));
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[r][mb] = mfma(wa[tp][mb], bv[r], acc[r][mb]);
+    }
+    // lane holds channels mb*16 + 4q + i of node (row, px)
+    uint16_t *so = &s_out[wv][0];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gy = y0 + wv * 4 + r, gx = x0 + px;
+      const size_t node = ((size_t)b * a.H + min(gy, a.H - 1)) * a.W + min(gx, a.W - 1);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int co = mb * 16 + 4 * q;
+        const v4f s = acc[r][mb];
+        u32x2 hv = u32x2{0u, 0u};
+        if (MODE == FWD_GELU) {
+          if (a.z && gy < a.H && gx < a.W) *(v4f *)(a.z + node * CH + co) = s;
+          hv = u32x2{pack2(gelu(s[0]), gelu(s[1])), pack2(gelu(s[2]), gelu(s[3]))};
+        } else if (MODE == FWD_OUT) {
+          if (mb == 0 && q == 0 && gy < a.H && gx < a.W) a.u[node] = s[0];
+        } else {
+          const v4f zp = *(const v4f *)(a.zprev + node * CH + co);
+          const float g0 = s[0] * gelu_d(zp[0]), g1 = s[1] * gelu_d(zp[1]);
+          const float g2 = s[2] * gelu_d(zp[2]), g3 = s[3] * gelu_d(zp[3]);
+          hv = u32x2{pack2(g0, g1), pack2(g2, g3)};
+        }
+        if (MODE != FWD_OUT) *(u32x2 *)(so + (r * TS + px) * OPS + co) = hv;
       }
     }
+    if (MODE != FWD_OUT) {
+      // the wave reads back what its own lanes wrote: no workgroup barrier
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+      const int nl = lane >> 2, c8 = lane & 3;   // node of the row, 16-byte chunk
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gy = y0 + wv * 4 + r, gx = x0 + nl;
+        const u32x4 v = *(const u32x4 *)(so + (r * TS + nl) * OPS + c8 * 8);
+        if (gy < a.H && gx < a.W) *(u32x4 *)(a.h + (((size_t)b * a.H + gy) * a.W + gx) * CH + c8 * 8) = v;
+      }
+    }
+    if (tn < ntiles) put(buf ^ 1, P);
+  };
+  while (true) {
+    step(0, pre0, pre1);
+    t += G;
+    if (t >= ntiles) break;
+    step(1, pre1, pre0);
+    t += G;
+    if (t >= ntiles) break;
   }
 }
 
@@ -455,6 +548,7 @@ hipError_t launch_cnn_extract(const FeatInst *fi_dev, int count, int H, int W, c
 
 struct adr_cnn {
   int H = 0, W = 0, maxB = 0, tx = 0, ty = 0;
+  int cus = 256;                    // compute units of the device (persistent grid size)
   hipStream_t stream = nullptr;
   float *param = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
   uint16_t *wf[NLAYER] = {}, *wd[NLAYER] = {};
@@ -522,7 +616,11 @@ hipError_t conv(const adr_cnn *N, int mode, int nout, const uint16_t *in, const 
   a.W = N->W;
   a.tx = N->tx;
   a.ty = N->ty;
-  const dim3 grid((unsigned)(nb * N->tx * N->ty)), blk(256);
+  a.nb = nb;
+  // persistent workgroups, as many as are resident at once (two per CU: the
+  // kernels hold the layer's weights in registers)
+  const int ntiles = nb * N->tx * N->ty;
+  const dim3 grid((unsigned)std::min(ntiles, 2 * N->cus)), blk(256);
   if (mode == FWD_GELU && nout == 32)
     hipLaunchKernelGGL((k_conv<32, FWD_GELU>), grid, blk, 0, N->stream, a);
   else if (mode == FWD_OUT && nout == 16)
@@ -615,6 +713,12 @@ adr_status adr_cnn_create(int32_t height, int32_t width, int32_t max_batch, void
   N->tx = (width + TS - 1) / TS;
   N->ty = (height + TS - 1) / TS;
   N->stream = (hipStream_t)stream;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      N->cus = cus;
+  }
   auto bail = [&](hipError_t e) {
     adr_cnn_destroy(N);
     return (adr_status)set_error(e == hipErrorOutOfMemory ? ADR_ERR_NOMEM : ADR_ERR_DEVICE,

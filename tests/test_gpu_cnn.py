@@ -89,7 +89,9 @@ def test_gradient_matches_reference(B, H, W):
     net.set_params(p)
     loss, g, u = net.gradient(xd, torch.from_numpy(t).cuda(), want_u=True)
     rl, rg, ru = ocnn.loss_and_grad(p.astype(np.float64), x, t.astype(np.float64), emulate=True)
-    assert abs(loss - rl) <= 1e-4 * rl
+    # the loss moves by 2 (u - t).du / N: with |du| <= U_TOL |u| and random
+    # targets (|u - t| >= |u|) its relative change is below about 2 U_TOL
+    assert abs(loss - rl) <= U_TOL * rl
     assert _rel(u.cpu().numpy(), ru) <= U_TOL
     off = 0
     for l, (ci, co) in enumerate(zip(ocnn.CIN, ocnn.COUT)):
