@@ -2,7 +2,7 @@
 
 Plain numpy, written from the network's definition rather than from the GPU
 kernels: six 3x3 cross-correlations with zero padding, channels
-9 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, exact GELU x*Phi(x) after the first
+10 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, exact GELU x*Phi(x) after the first
 five, mean squared error over the interior nodes, Adam.  Every sum is in
 FP64.  With ``emulate=True`` the values the network stores in bfloat16
 (input fields, weights, hidden activations, and the gradients entering each
