@@ -80,7 +80,7 @@ def parse():
                     default="single")
     ap.add_argument("--pmc-fetch", default="", help="traffic: rocprofv3 output folder of the FETCH_SIZE pass")
     ap.add_argument("--pmc-write", default="", help="traffic: rocprofv3 output folder of the WRITE_SIZE pass")
-    ap.add_argument("--large-maxit", type=int, default=6000, help="large: pass limit of the Dirichlet solves")
+    ap.add_argument("--large-maxit", type=int, default=10000, help="large: pass limit of the Dirichlet solves")
     ap.add_argument("--heldout", type=int, default=1000, help="warmstart: held-out instances")
     ap.add_argument("--single-sample", type=int, default=128,
                     help="warmstart: instances also timed one at a time")
@@ -328,16 +328,23 @@ def run_warmstart(args):
     wall = time.perf_counter() - t0
     s = ev["summary"]
     k = max(s["single_instances"], 1)
-    # network throughput on the matrix cores: inference and one training step
-    # of a batch of 64 instances (nominal FLOPs of the six 3x3 layers with the
-    # channel padding the kernels compute: 32 in, 32 out, last layer 16 out)
+    # network throughput: inference and one training step of a batch of 64
+    # instances.  Algorithmic work of the six 3x3 layers (10 -> 32 -> ... ->
+    # 32 -> 1 channels; the zero channels the kernels pad to are not counted):
+    # 2 * 9 * sum(cin * cout) flop per node, and per node the bytes a
+    # layer-by-layer forward pass must move: each layer reads its input
+    # (10 channels, then 32, bfloat16) and writes its output (32 bfloat16
+    # channels, the last one FP32 u).  At 120 flop/B the pass sits below the
+    # bf16 ridge (2.5 PFLOP/s / 8 TB/s = 312 flop/B): it is HBM-bound.
     H = n + 2
     B = 64
     xin = torch.zeros((B, H, H, 32), dtype=torch.bfloat16, device="cuda")
     xin[..., :10] = torch.randn((B, H, H, 10), device="cuda").to(torch.bfloat16)
     u = torch.empty((B, H, H), dtype=torch.float32, device="cuda")
     tgt = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
-    fwd_flop = 2.0 * B * H * H * 9 * 32 * (5 * 32 + 16)
+    cio = [(10, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1)]
+    fwd_flop = 2.0 * B * H * H * 9 * sum(ci * co for ci, co in cio)
+    fwd_bytes = float(B * H * H * (10 * 2 + 5 * 32 * 2 + 5 * 32 * 2 + 4))
     stream = torch.cuda.current_stream()
     net.forward(xin, out=u)
     torch.cuda.synchronize()
@@ -349,7 +356,7 @@ def run_warmstart(args):
     e1.synchronize()
     fwd_ms = e0.elapsed_time(e1) / 10
     # training: forward + input gradients of layers 2..6 + weight gradients of all six
-    step_flop = fwd_flop + 2.0 * B * H * H * 9 * 32 * (5 * 32) + fwd_flop
+    step_flop = 2 * fwd_flop + 2.0 * B * H * H * 9 * sum(ci * co for ci, co in cio[1:])
     net2 = adr.WarmStartNet(H, H, B)
     net2.set_params(np.load(tw.DEFAULT_WEIGHTS, allow_pickle=False))
     net2.train_step(xin, tgt, lr=0.0)
@@ -359,12 +366,17 @@ def run_warmstart(args):
         net2.train_step(xin, tgt, lr=0.0)
     torch.cuda.synchronize()
     step_ms = (time.perf_counter() - t1) * 1e3 / 5
-    mfma = dict(bound="mfma", kernel="k_conv (6-layer forward, batch 64, 258x258)",
-                achieved=round(fwd_flop / (fwd_ms * 1e-3) / 1e12, 1), peak=2500.0, unit="TFLOP/s",
-                frac=round(fwd_flop / (fwd_ms * 1e-3) / 1e12 / 2500.0, 4), traffic=None,
+    fwd_tflops = fwd_flop / (fwd_ms * 1e-3) / 1e12
+    mfma = dict(bound="hbm", kernel="k_conv (6-layer forward, batch 64, 258x258)",
+                achieved=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), traffic=None,
+                algorithmic_bytes=fwd_bytes, algorithmic_flop=fwd_flop,
+                flop_per_byte=round(fwd_flop / fwd_bytes, 1),
+                tflops=round(fwd_tflops, 1), frac_of_bf16_peak=round(fwd_tflops / 2500.0, 4),
                 forward_ms=round(fwd_ms, 3), train_step_ms=round(step_ms, 3),
                 train_step_tflops=round(step_flop / (step_ms * 1e-3) / 1e12, 1))
-    log("  network: forward %.2f ms (%.0f TFLOP/s), training step %.2f ms" % (fwd_ms, mfma["achieved"], step_ms))
+    log("  network: forward %.2f ms (%.0f GB/s, %.0f TFLOP/s), training step %.2f ms" %
+        (fwd_ms, mfma["achieved"], fwd_tflops, step_ms))
     out = {
         "metric": "time to rel-resid 1e-10 per instance from the learned guess (single-instance solves)",
         "value": round(s["single_warm_ms"] / k / 1e3, 5), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
