@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", choices=("single", "batch", "warmstart", "kernels", "large", "traffic"),
+    ap.add_argument("--workload", choices=("single", "batch", "warmstart", "network", "kernels", "large", "traffic"),
                     default="single")
     ap.add_argument("--pmc-fetch", default="", help="traffic: rocprofv3 output folder of the FETCH_SIZE pass")
     ap.add_argument("--pmc-write", default="", help="traffic: rocprofv3 output folder of the WRITE_SIZE pass")
@@ -304,6 +304,87 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def network_roofline(weights, reps=10):
+    """Forward pass and one training step of the warm-start network on a batch
+    of 64 instances at 258 x 258 nodes (random inputs in the ten field
+    channels), timed with events on the current stream."""
+    import torch
+    import paper_1308_5215_amd as adr
+
+    n = 256
+    net = adr.WarmStartNet(n + 2, n + 2, 64)
+    net.set_params(weights)
+    # network throughput: inference and one training step of a batch of 64
+    # instances.  Algorithmic work of the six 3x3 layers (10 -> 32 -> ... ->
+    # 32 -> 1 channels; the zero channels the kernels pad to are not counted):
+    # 2 * 9 * sum(cin * cout) flop per node, and per node the bytes a
+    # layer-by-layer forward pass must move: each layer reads its input
+    # (10 channels, then 32, bfloat16) and writes its output (32 bfloat16
+    # channels, the last one FP32 u).  At 120 flop/B the pass sits below the
+    # bf16 ridge (2.5 PFLOP/s / 8 TB/s = 312 flop/B): it is HBM-bound.
+    H = n + 2
+    B = 64
+    xin = torch.zeros((B, H, H, 32), dtype=torch.bfloat16, device="cuda")
+    xin[..., :10] = torch.randn((B, H, H, 10), device="cuda").to(torch.bfloat16)
+    u = torch.empty((B, H, H), dtype=torch.float32, device="cuda")
+    tgt = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
+    cio = [(10, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1)]
+    fwd_flop = 2.0 * B * H * H * 9 * sum(ci * co for ci, co in cio)
+    fwd_bytes = float(B * H * H * (10 * 2 + 5 * 32 * 2 + 5 * 32 * 2 + 4))
+    stream = torch.cuda.current_stream()
+    net.forward(xin, out=u)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        net.forward(xin, out=u)
+    e1.record(stream)
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    # training: forward + input gradients of layers 2..6 + weight gradients of all six
+    step_flop = 2 * fwd_flop + 2.0 * B * H * H * 9 * sum(ci * co for ci, co in cio[1:])
+    net2 = adr.WarmStartNet(H, H, B)
+    net2.set_params(weights)
+    net2.train_step(xin, tgt, lr=0.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(5):
+        net2.train_step(xin, tgt, lr=0.0)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t1) * 1e3 / 5
+    fwd_tflops = fwd_flop / (fwd_ms * 1e-3) / 1e12
+    return dict(bound="hbm", kernel="k_conv (6-layer forward, batch 64, 258x258)",
+                achieved=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), traffic=None,
+                algorithmic_bytes=fwd_bytes, algorithmic_flop=fwd_flop,
+                flop_per_byte=round(fwd_flop / fwd_bytes, 1),
+                tflops=round(fwd_tflops, 1), frac_of_bf16_peak=round(fwd_tflops / 2500.0, 4),
+                forward_ms=round(fwd_ms, 3), train_step_ms=round(step_ms, 3),
+                train_step_tflops=round(step_flop / (step_ms * 1e-3) / 1e12, 1))
+
+
+def run_network(args):
+    """The warm-start network alone: forward pass and training step of a batch
+    of 64 instances at 258 x 258 with the committed weights (the per-layer
+    profile of the network is taken on this workload)."""
+    import numpy as np
+    import torch
+    from paper_1308_5215_amd import train_warmstart as tw
+
+    torch.cuda.set_device(0)
+    r = network_roofline(np.load(tw.DEFAULT_WEIGHTS, allow_pickle=False), reps=args.steps * 10)
+    out = {"metric": "warm-start network forward pass, batch 64 at 258x258", "value": r["forward_ms"] / 1e3,
+           "unit": "s", "n_gpus": 1, "steps": args.steps * 10, "warmup": 1, "ms_per_step": r["forward_ms"],
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": "6 x conv3x3, 10->32->...->32->1, GELU, bf16 activations and weights, fp32 "
+                                  "accumulate; batch 64, 258 x 258 nodes"},
+           "roofline": r}
+    log("  network: forward %.3f ms (%.0f GB/s, %.0f TFLOP/s), training step %.2f ms" %
+        (r["forward_ms"], r["achieved"], r["tflops"], r["train_step_ms"]))
+    print(json.dumps(out), flush=True)
+
+
 def run_warmstart(args):
     """Learned initial guess: held-out 256 x 256 instances (seeds 100000...,
     eps log-uniform in [1e-3, 1], X, Y in [0.5, 2], Dirichlet or Neumann outer
@@ -328,55 +409,9 @@ def run_warmstart(args):
     wall = time.perf_counter() - t0
     s = ev["summary"]
     k = max(s["single_instances"], 1)
-    # network throughput: inference and one training step of a batch of 64
-    # instances.  Algorithmic work of the six 3x3 layers (10 -> 32 -> ... ->
-    # 32 -> 1 channels; the zero channels the kernels pad to are not counted):
-    # 2 * 9 * sum(cin * cout) flop per node, and per node the bytes a
-    # layer-by-layer forward pass must move: each layer reads its input
-    # (10 channels, then 32, bfloat16) and writes its output (32 bfloat16
-    # channels, the last one FP32 u).  At 120 flop/B the pass sits below the
-    # bf16 ridge (2.5 PFLOP/s / 8 TB/s = 312 flop/B): it is HBM-bound.
-    H = n + 2
-    B = 64
-    xin = torch.zeros((B, H, H, 32), dtype=torch.bfloat16, device="cuda")
-    xin[..., :10] = torch.randn((B, H, H, 10), device="cuda").to(torch.bfloat16)
-    u = torch.empty((B, H, H), dtype=torch.float32, device="cuda")
-    tgt = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
-    cio = [(10, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1)]
-    fwd_flop = 2.0 * B * H * H * 9 * sum(ci * co for ci, co in cio)
-    fwd_bytes = float(B * H * H * (10 * 2 + 5 * 32 * 2 + 5 * 32 * 2 + 4))
-    stream = torch.cuda.current_stream()
-    net.forward(xin, out=u)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        net.forward(xin, out=u)
-    e1.record(stream)
-    e1.synchronize()
-    fwd_ms = e0.elapsed_time(e1) / 10
-    # training: forward + input gradients of layers 2..6 + weight gradients of all six
-    step_flop = 2 * fwd_flop + 2.0 * B * H * H * 9 * sum(ci * co for ci, co in cio[1:])
-    net2 = adr.WarmStartNet(H, H, B)
-    net2.set_params(np.load(tw.DEFAULT_WEIGHTS, allow_pickle=False))
-    net2.train_step(xin, tgt, lr=0.0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(5):
-        net2.train_step(xin, tgt, lr=0.0)
-    torch.cuda.synchronize()
-    step_ms = (time.perf_counter() - t1) * 1e3 / 5
-    fwd_tflops = fwd_flop / (fwd_ms * 1e-3) / 1e12
-    mfma = dict(bound="hbm", kernel="k_conv (6-layer forward, batch 64, 258x258)",
-                achieved=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), traffic=None,
-                algorithmic_bytes=fwd_bytes, algorithmic_flop=fwd_flop,
-                flop_per_byte=round(fwd_flop / fwd_bytes, 1),
-                tflops=round(fwd_tflops, 1), frac_of_bf16_peak=round(fwd_tflops / 2500.0, 4),
-                forward_ms=round(fwd_ms, 3), train_step_ms=round(step_ms, 3),
-                train_step_tflops=round(step_flop / (step_ms * 1e-3) / 1e12, 1))
+    mfma = network_roofline(np.load(tw.DEFAULT_WEIGHTS, allow_pickle=False))
     log("  network: forward %.2f ms (%.0f GB/s, %.0f TFLOP/s), training step %.2f ms" %
-        (fwd_ms, mfma["achieved"], fwd_tflops, step_ms))
+        (mfma["forward_ms"], mfma["achieved"], mfma["tflops"], mfma["train_step_ms"]))
     out = {
         "metric": "time to rel-resid 1e-10 per instance from the learned guess (single-instance solves)",
         "value": round(s["single_warm_ms"] / k / 1e3, 5), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -682,6 +717,8 @@ def main():
         return run_batch(args)
     if args.workload == "warmstart":
         return run_warmstart(args)
+    if args.workload == "network":
+        return run_network(args)
     if args.workload == "kernels":
         return run_kernels(args)
     if args.workload == "traffic":

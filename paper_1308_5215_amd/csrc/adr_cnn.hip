@@ -72,7 +72,7 @@ __device__ __forceinline__ uint32_t pack2(float a, float b) {
 // exponential, a degree-5 polynomial), written for Phi directly: with
 // a = |z| / sqrt(2), t = 1 / (1 + p a) and h =
 // (q(t) / 2) exp(-z^2 / 2), Phi(z) = 1 - h for z >= 0 and h for z < 0 (the
-// halves folded into the coefficients)
+// halves folded into the coefficients), so z Phi(z) = max(z, 0) - |z| h
 __device__ __forceinline__ float gelu(float z) {
   const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, fabsf(z), 1.0f));
   float q = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
@@ -81,7 +81,8 @@ __device__ __forceinline__ float gelu(float z) {
   q = fmaf(q, t, 0.5f * 0.254829592f);
   q *= t;
   const float h = q * __builtin_amdgcn_exp2f((z * (-0.5f * 1.4426950408889634f)) * z);
-  return z * (z >= 0.0f ? 1.0f - h : h);
+  // z Phi(z) = max(z, 0) - |z| h for either sign of z
+  return fmaf(-fabsf(z), h, fmaxf(z, 0.0f));
 }
 __device__ __forceinline__ float gelu_d(float z) {
   const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
@@ -95,14 +96,15 @@ __device__ __forceinline__ v4f mfma(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-enum { FWD_GELU = 0, FWD_OUT = 1, BWD_GELU = 2 };
+// FWD_GELU_Z: FWD_GELU that also stores the FP32 pre-activations (training)
+enum { FWD_GELU = 0, FWD_OUT = 1, BWD_GELU = 2, FWD_GELU_Z = 3 };
 
 struct ConvArgs {
   const uint16_t *in;    // [B][H][W][32]
   const uint16_t *w;     // [9][COUT][32]: tap, output channel, input channel
   const float *bias;     // [COUT] (forward modes)
-  float *z;              // FWD_GELU: pre-activations [B][H][W][32], or null
-  uint16_t *h;           // FWD_GELU: activations; BWD_GELU: input gradient
+  float *z;              // FWD_GELU_Z: pre-activations [B][H][W][32]
+  uint16_t *h;           // FWD_GELU(_Z): activations; BWD_GELU: input gradient
   const float *zprev;    // BWD_GELU: pre-activations of the layer below
   float *u;              // FWD_OUT: [B][H][W]
   int H, W, tx, ty, nb;
@@ -110,10 +112,9 @@ struct ConvArgs {
 
 // 16 x 16 output tiles; wave w computes tile rows 4w..4w+3.  Persistent: a
 // workgroup loads the layer's weights into registers once and takes tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ...; the input tile two steps ahead is
-// loaded into registers (two sets, alternating) while the current one's
-// products run, and the one a step ahead is written to the other half of a
-// double-buffered LDS tile afterwards.
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's input is loaded
+// into registers while the current one's products run and is written to the
+// other half of a double-buffered LDS tile afterwards.
 template <int NOUT, int MODE>
 __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
   constexpr int PS = 40;  // LDS node stride in bf16 (80 B: rows of 16 B reads do not collide)
@@ -136,10 +137,28 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
     y0 = tpy * TS;
     x0 = tpx * TS;
   };
-  u32x4 pre0[NLD], pre1[NLD];
+  u32x4 pre[NLD];
+  // byte offset of each staging load from the halo tile's first node, the
+  // same for every tile
+  unsigned hoff[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = tid + k * 256, node = i >> 2, r = node / HALO;
+    hoff[k] = (unsigned)(((r * a.W + (node - r * HALO)) * CH + (i & 3) * 8) * 2);
+  }
   auto fetch = [&](int tile, u32x4 (&pre)[NLD]) {
     int b, y0, x0;
     origin(tile, b, y0, x0);
+    if (y0 >= 1 && x0 >= 1 && y0 + HALO - 1 <= a.H && x0 + HALO - 1 <= a.W) {
+      // the whole halo lies in the grid: no bounds tests
+      const char *tb = (const char *)(a.in + (((size_t)b * a.H + (y0 - 1)) * a.W + (x0 - 1)) * CH);
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) {
+        pre[k] = u32x4{0u, 0u, 0u, 0u};
+        if (tid + k * 256 < HALO * HALO * 4) pre[k] = *(const u32x4 *)(tb + hoff[k]);
+      }
+      return;
+    }
     const uint16_t *inb = a.in + (size_t)b * a.H * a.W * CH;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
@@ -174,15 +193,13 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
                                                    : v4f{a.bias[co], a.bias[co + 1], a.bias[co + 2], a.bias[co + 3]});
   }
   const int G = gridDim.x;
-  fetch(t, pre0);
-  put(0, pre0);
-  if (t + G < ntiles) fetch(t + G, pre1);
-  // step for tile t from LDS half `buf`: tile t + 2G is fetched into set F
-  // while it runs, then tile t + G (fetched a step earlier into set P) is
-  // put into the other half
-  auto step = [&](int buf, u32x4 (&F)[NLD], const u32x4 (&P)[NLD]) {
+  fetch(t, pre);
+  put(0, pre);
+  // step for tile t from LDS half `buf`: tile t + G is fetched into
+  // registers while it runs and put into the other half afterwards
+  auto step = [&](int buf) {
     const int tn = t + G;
-    if (t + 2 * G < ntiles) fetch(t + 2 * G, F);
+    if (tn < ntiles) fetch(tn, pre);
     __syncthreads();              // this tile staged; the other half no longer read
     int b, y0, x0;
     origin(t, b, y0, x0);
@@ -217,8 +234,8 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
         const int co = mb * 16 + 4 * q;
         const v4f s = acc[r][mb];
         u32x2 hv = u32x2{0u, 0u};
-        if (MODE == FWD_GELU) {
-          if (a.z && gy < a.H && gx < a.W) *(v4f *)(a.z + node * CH + co) = s;
+        if (MODE == FWD_GELU || MODE == FWD_GELU_Z) {
+          if (MODE == FWD_GELU_Z && gy < a.H && gx < a.W) *(v4f *)(a.z + node * CH + co) = s;
           hv = u32x2{pack2(gelu(s[0]), gelu(s[1])), pack2(gelu(s[2]), gelu(s[3]))};
         } else if (MODE == FWD_OUT) {
           if (mb == 0 && q == 0 && gy < a.H && gx < a.W) a.u[node] = s[0];
@@ -237,23 +254,25 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
       const int nl = lane >> 2, c8 = lane & 3;   // node of the row, 16-byte chunk
+      if (y0 + TS <= a.H && x0 + TS <= a.W) {
+        // every node of the tile is in the grid
+        char *ob = (char *)(a.h + (((size_t)b * a.H + y0 + wv * 4) * a.W + x0) * CH);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gy = y0 + wv * 4 + r, gx = x0 + nl;
-        const u32x4 v = *(const u32x4 *)(so + (r * TS + nl) * OPS + c8 * 8);
-        if (gy < a.H && gx < a.W) *(u32x4 *)(a.h + (((size_t)b * a.H + gy) * a.W + gx) * CH + c8 * 8) = v;
+        for (int r = 0; r < 4; ++r)
+          *(u32x4 *)(ob + ((unsigned)((r * a.W + nl) * CH + c8 * 8) * 2u)) =
+              *(const u32x4 *)(so + (r * TS + nl) * OPS + c8 * 8);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gy = y0 + wv * 4 + r, gx = x0 + nl;
+          const u32x4 v = *(const u32x4 *)(so + (r * TS + nl) * OPS + c8 * 8);
+          if (gy < a.H && gx < a.W) *(u32x4 *)(a.h + (((size_t)b * a.H + gy) * a.W + gx) * CH + c8 * 8) = v;
+        }
       }
     }
-    if (tn < ntiles) put(buf ^ 1, P);
+    if (tn < ntiles) put(buf ^ 1, pre);
   };
-  while (true) {
-    step(0, pre0, pre1);
-    t += G;
-    if (t >= ntiles) break;
-    step(1, pre1, pre0);
-    t += G;
-    if (t >= ntiles) break;
-  }
+  for (int buf = 0; t < ntiles; t += G, buf ^= 1) step(buf);
 }
 
 struct WgArgs {
@@ -621,7 +640,9 @@ hipError_t conv(const adr_cnn *N, int mode, int nout, const uint16_t *in, const 
   // kernels hold the layer's weights in registers)
   const int ntiles = nb * N->tx * N->ty;
   const dim3 grid((unsigned)std::min(ntiles, 2 * N->cus)), blk(256);
-  if (mode == FWD_GELU && nout == 32)
+  if (mode == FWD_GELU && nout == 32 && z)
+    hipLaunchKernelGGL((k_conv<32, FWD_GELU_Z>), grid, blk, 0, N->stream, a);
+  else if (mode == FWD_GELU && nout == 32)
     hipLaunchKernelGGL((k_conv<32, FWD_GELU>), grid, blk, 0, N->stream, a);
   else if (mode == FWD_OUT && nout == 16)
     hipLaunchKernelGGL((k_conv<16, FWD_OUT>), grid, blk, 0, N->stream, a);
