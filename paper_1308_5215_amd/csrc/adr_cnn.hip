@@ -112,7 +112,7 @@ struct ConvArgs {
 
 // 16 x 16 output tiles; wave w computes tile rows 4w..4w+3.  Persistent: a
 // workgroup loads the layer's weights into registers once and takes tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's input is loaded
+// in turn (dealt per XCD, below); the next tile's input is loaded
 // into registers while the current one's products run and is written to the
 // other half of a double-buffered LDS tile afterwards.
 template <int NOUT, int MODE>
@@ -128,8 +128,18 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int px = lane & 15, q = lane >> 4;
   const int ntiles = a.nb * a.tx * a.ty;
-  int t = blockIdx.x;
-  if (t >= ntiles) return;
+  // Tiles are dealt per XCD: workgroup b runs on XCD b mod 8 and takes the
+  // tiles of that XCD's contiguous eighth of the tile list in turn, so the
+  // tiles in flight on one XCD are neighbours and find much of their halo in
+  // its L2 (a mapping that only placement depends on, not correctness).
+  const int G = gridDim.x;
+  const bool by_xcd = (G & 7) == 0 && ntiles >= G;
+  const int per = by_xcd ? (ntiles + 7) / 8 : ntiles;   // tiles per XCD
+  const int stride = by_xcd ? G / 8 : G;                 // workgroups per XCD
+  const int t_lo = by_xcd ? (int)(blockIdx.x & 7) * per : 0;
+  const int t_hi = by_xcd ? min(t_lo + per, ntiles) : ntiles;
+  int t = t_lo + (by_xcd ? (int)(blockIdx.x >> 3) : (int)blockIdx.x);
+  if (t >= t_hi) return;
   auto origin = [&](int tile, int &b, int &y0, int &x0) {
     const int tpx = tile % a.tx, rest = tile / a.tx;
     const int tpy = rest % a.ty;
@@ -192,14 +202,13 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
                                 : (MODE == FWD_OUT ? v4f{a.bias[0], 0.f, 0.f, 0.f}
                                                    : v4f{a.bias[co], a.bias[co + 1], a.bias[co + 2], a.bias[co + 3]});
   }
-  const int G = gridDim.x;
   fetch(t, pre);
   put(0, pre);
   // step for tile t from LDS half `buf`: tile t + G is fetched into
   // registers while it runs and put into the other half afterwards
   auto step = [&](int buf) {
-    const int tn = t + G;
-    if (tn < ntiles) fetch(tn, pre);
+    const int tn = t + stride;
+    if (tn < t_hi) fetch(tn, pre);
     __syncthreads();              // this tile staged; the other half no longer read
     int b, y0, x0;
     origin(t, b, y0, x0);
@@ -270,9 +279,9 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
         }
       }
     }
-    if (tn < ntiles) put(buf ^ 1, pre);
+    if (tn < t_hi) put(buf ^ 1, pre);
   };
-  for (int buf = 0; t < ntiles; t += G, buf ^= 1) step(buf);
+  for (int buf = 0; t < t_hi; t += stride, buf ^= 1) step(buf);
 }
 
 struct WgArgs {
