@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+RING_NAMES = {0: "deep", 1: "compact", 2: "paired"}   # adr_sweep_ring
 
 
 def kernel_bytes(precision="fp64", tables=True):
@@ -207,7 +208,7 @@ def run_batch(args):
         b, rows, ms_apply, res = batch_once()
         times.append(res.solve_ms)
         log("  batch solve %.1f ms, rows %d, %s ring (autotuned, %.2f ms per M^-1)" %
-            (res.solve_ms, rows[0], "compact" if rows[1] else "deep", ms_apply))
+            (res.solve_ms, rows[0], RING_NAMES.get(rows[1], str(rows[1])), ms_apply))
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
     st = np.asarray(res.status)
@@ -295,7 +296,7 @@ def run_batch(args):
                        "speedup_batched": round(seq_s / batch_s, 2) if batch_s > 0 else None,
                        "max_rel_diff_vs_batched": maxdiff},
         "sweep_rows": rows[0],
-        "sweep_ring": "compact" if rows[1] else "deep",
+        "sweep_ring": RING_NAMES.get(rows[1], str(rows[1])),
         "cpu_baseline": cpu,
     }
     with open(os.path.join(ROOT, "gpurun_out", "batch_instances.json") if os.path.isdir(

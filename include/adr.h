@@ -364,9 +364,10 @@ size_t adr_device_bytes(const adr_problem *p);
 
 /* Sweep geometry: rows per strip (R = 15 or 31) for the wavefront kernels,
  * or 0 for the default (31, also the height a new problem starts with).
- * Also returns 31-row strips to the automatic ring choice (two workgroups
- * per CU once the strips exceed 1.5 per CU -- 384 on 256 CUs -- else one).  Results do not depend on
- * it.  For tuning and tests. */
+ * Also returns 31-row strips to the automatic ring choice (the compact ring
+ * while the strips fit one per CU or once they exceed 1.5 per CU -- 384 on
+ * 256 CUs -- the deep ring in between).  Results do not depend on it.  For
+ * tuning and tests. */
 adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
 
 /* Ring of the 31-row sweeps: -1 automatic (the default), 0 one workgroup per

@@ -201,8 +201,13 @@ struct adr_problem {
   SweepSync sync() const { return SweepSync{ticket, handoff, err}; }
   Dia dia() const { return Dia{S, W, C, E, N}; }
   const double *stencil_tab() const { return (has_tab && tab_on) ? tab : nullptr; }
-  // automatic: compact once the strips exceed 1.5 per CU (384 on 256 CUs)
-  int ring_compact() const { return compact >= 0 ? compact : (2 * nstrips > 3 * cus ? 1 : 0); }
+  // automatic: the compact ring when every strip has a CU of its own (its
+  // smaller register and LDS footprint is 1 % faster per pass at 2048^2 and
+  // 4096^2) or once the strips exceed 1.5 per CU (384 on 256 CUs); the deep
+  // ring in between, where strips beyond one per CU would share a CU
+  int ring_compact() const {
+    return compact >= 0 ? compact : ((nstrips <= cus || 2 * nstrips > 3 * cus) ? 1 : 0);
+  }
   // XCD-grouped strips: a single instance whose strips all fit on the
   // device at once (one workgroup per CU on the deep ring) places
   // consecutive strips on one XCD (workgroup b runs on XCD b mod 8)

@@ -237,8 +237,10 @@ struct SweepShape {
 
 }  // namespace
 
+// CMP: two workgroups share a CU, so each wave gets at most a quarter of a
+// SIMD's registers (four waves per SIMD)
 template <int R, int OP, int PREC, bool TAB, bool CMP>
-__global__ __launch_bounds__(ADR_SWEEP_THREADS) void k_sweep_ws(SweepParams p) {
+__global__ __launch_bounds__(ADR_SWEEP_THREADS, CMP ? 4 : 1) void k_sweep_ws(SweepParams p) {
   static_assert(!TAB || OP == 1 || PREC == 0, "the L sweep forms its factors from tables only in FP64");
   using TF = typename std::conditional<PREC == 0, double, float>::type;
   using CT = typename std::conditional<PREC == 2, float, double>::type;

@@ -549,7 +549,7 @@ def test_sweep_ring_changes_no_bit(adr, precision):
         assert equal(x0, x1) and equal(r0.hist_l2, r1.hist_l2) and equal(r0.hist_max, r1.hist_max)
     prob.use_stencil_tables(True)
     prob.set_sweep_ring(-1)
-    assert prob.sweep_ring == 0   # three strips: the automatic choice is the deep ring
+    assert prob.sweep_ring == 1   # three strips, one per CU: the automatic choice is the compact ring
     with pytest.raises(adr.AdrError):
         prob.set_sweep_ring(2)
 
