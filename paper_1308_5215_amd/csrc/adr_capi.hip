@@ -220,7 +220,11 @@ struct adr_problem {
 #endif
   }
   BatchGeom geom() const {
-    return BatchGeom{d_inst, count, nblk, nstrips, rows, ring_compact(), xcd_group(), d_sorder};
+    // the compact ring with three loader waves instead of five where every
+    // strip has a CU of its own: the strips then wait on each other, not on
+    // their loads, and fewer loads in flight shorten the hand-offs
+    const int ring = ring_compact() == 1 && nstrips <= cus ? 2 : ring_compact();
+    return BatchGeom{d_inst, count, nblk, nstrips, rows, ring, xcd_group(), d_sorder};
   }
 };
 

@@ -82,7 +82,8 @@ struct BatchGeom {
   int nblk;           // total streaming blocks
   int nstrips;        // total strips
   int rows;           // strip height R
-  int compact;        // 31-row sweeps: 76 KB ring, two workgroups per CU (see adr_sweeps.hip)
+  int compact;        // 31-row sweeps: 0 deep ring; 1 compact ring (76 KB, two workgroups per CU);
+                      // 2 compact ring with three loader waves (strips at most one per CU)
   int xcd_group;      // > 0: strips by workgroup index, xcd_group consecutive strips per XCD
   const int *sorder;  // device: instances in strip-ticket order (largest work first); strip0 ascends along it
 };

@@ -215,12 +215,12 @@ __device__ __forceinline__ int lds_peek(int *c) {
 }
 __device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local"); }
 
-template <int R, int NIN, int CTB, bool CMP>
+template <int R, int NIN, int CTB, bool CMP, int NTH>
 struct SweepShape {
   static constexpr int W = 16;                      // columns per chunk
   static constexpr int L = R + 1;                   // tile rows (row 0 = ghost)
   static constexpr int PITCH = W + 2;               // 16-byte aligned rows
-  static constexpr int NT = ADR_SWEEP_THREADS;      // threads per workgroup
+  static constexpr int NT = NTH;                    // threads per workgroup
   static constexpr int NLD = NT / 64 - 3;           // loader waves
   // 76 KB (two workgroups per CU) for R = 15 and for compact 31-row strips
   // (tiles of at most three arrays, four or more slots), else 150 KB (one
@@ -239,8 +239,9 @@ struct SweepShape {
 
 // CMP: two workgroups share a CU, so each wave gets at most a quarter of a
 // SIMD's registers (four waves per SIMD)
-template <int R, int OP, int PREC, bool TAB, bool CMP>
-__global__ __launch_bounds__(ADR_SWEEP_THREADS, CMP ? 4 : 1) void k_sweep_ws(SweepParams p) {
+// NTH: threads per workgroup (three waves plus the loaders)
+template <int R, int OP, int PREC, bool TAB, bool CMP, int NTH>
+__global__ __launch_bounds__(NTH, CMP ? 4 : 1) void k_sweep_ws(SweepParams p) {
   static_assert(!TAB || OP == 1 || PREC == 0, "the L sweep forms its factors from tables only in FP64");
   using TF = typename std::conditional<PREC == 0, double, float>::type;
   using CT = typename std::conditional<PREC == 2, float, double>::type;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(ADR_SWEEP_THREADS, CMP ? 4 : 1) void k_sweep_ws(Swe
   // a register of that row's lane: its ring tiles hold y, E and invd only.
   constexpr bool NREG = (OP == 1) && TAB;
   constexpr int NL = NREG ? 3 : NIN;   // arrays per ring tile (U: invd last)
-  using Sh = SweepShape<R, NL, (int)sizeof(CT), CMP>;
+  using Sh = SweepShape<R, NL, (int)sizeof(CT), CMP, NTH>;
   constexpr int W = Sh::W, L = Sh::L, PITCH = Sh::PITCH, NC = Sh::NC, NT = Sh::NT, NLD = Sh::NLD;
   constexpr int RPP = Sh::RPP, NP = Sh::NP;
   constexpr int LDEPTH = (R > 15 && !CMP) ? LDEPTH_DEEP : 1;
@@ -925,12 +926,19 @@ static hipError_t launch_sweep_t(const SweepParams &p, hipStream_t s) {
   constexpr bool CAN_CMP = OP == 0 || TAB;   // three arrays per tile
   const int grid = p.g.xcd_group > 0 ? 8 * p.g.xcd_group : p.g.nstrips;
   switch (p.g.rows) {
-    case 15: hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC, TAB, false>), dim3(p.g.nstrips), dim3(ADR_SWEEP_THREADS), 0, s, p); break;
+    case 15:
+      hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC, TAB, false, ADR_SWEEP_THREADS>), dim3(p.g.nstrips),
+                         dim3(ADR_SWEEP_THREADS), 0, s, p);
+      break;
     case 31:
-      if (CAN_CMP && p.g.compact)
-        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, CAN_CMP>), dim3(p.g.nstrips), dim3(ADR_SWEEP_THREADS), 0, s, p);
+      if (CAN_CMP && p.g.compact == 2)   // compact ring, three loader waves
+        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, CAN_CMP, 384>), dim3(p.g.nstrips), dim3(384), 0, s, p);
+      else if (CAN_CMP && p.g.compact)
+        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, CAN_CMP, ADR_SWEEP_THREADS>), dim3(p.g.nstrips),
+                           dim3(ADR_SWEEP_THREADS), 0, s, p);
       else
-        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, false>), dim3(grid), dim3(ADR_SWEEP_THREADS), 0, s, p);
+        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, false, ADR_SWEEP_THREADS>), dim3(grid),
+                           dim3(ADR_SWEEP_THREADS), 0, s, p);
       break;
 
     default: return hipErrorInvalidValue;
