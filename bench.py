@@ -81,6 +81,8 @@ def parse():
                     default="single")
     ap.add_argument("--pmc-fetch", default="", help="traffic: rocprofv3 output folder of the FETCH_SIZE pass")
     ap.add_argument("--pmc-write", default="", help="traffic: rocprofv3 output folder of the WRITE_SIZE pass")
+    ap.add_argument("--pmc-net-fetch", default="", help="traffic: FETCH_SIZE folder of --workload network")
+    ap.add_argument("--pmc-net-write", default="", help="traffic: WRITE_SIZE folder of --workload network")
     ap.add_argument("--large-maxit", type=int, default=10000, help="large: pass limit of the Dirichlet solves")
     ap.add_argument("--heldout", type=int, default=1000, help="warmstart: held-out instances")
     ap.add_argument("--single-sample", type=int, default=128,
@@ -354,9 +356,17 @@ def network_roofline(weights, reps=10):
     torch.cuda.synchronize()
     step_ms = (time.perf_counter() - t1) * 1e3 / 5
     fwd_tflops = fwd_flop / (fwd_ms * 1e-3) / 1e12
+    traffic = None
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            e = json.load(fh).get("network_258_b64")
+        if e and e.get("source_hash") == network_source_hash():
+            traffic = float(e["bytes_per_forward"])
+    except (OSError, ValueError):
+        pass
     return dict(bound="hbm", kernel="k_conv (6-layer forward, batch 64, 258x258)",
                 achieved=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), traffic=None,
+                frac=round(fwd_bytes / (fwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), traffic=traffic,
                 algorithmic_bytes=fwd_bytes, algorithmic_flop=fwd_flop,
                 flop_per_byte=round(fwd_flop / fwd_bytes, 1),
                 tflops=round(fwd_tflops, 1), frac_of_bf16_peak=round(fwd_tflops / 2500.0, 4),
@@ -623,12 +633,43 @@ def read_pmc(folder, counter):
     return vals
 
 
+def network_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1308_5215_amd", "csrc", "adr_cnn.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_forward_pmc(folder, counter):
+    """Counter totals of each six-layer forward pass (five k_conv<32, 0>
+    dispatches followed by one k_conv<16, 1>) in a rocprofv3 --pmc folder of
+    `--workload network`."""
+    import csv
+    import glob
+    disp = {}
+    for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = row.get("Kernel_Name", "")
+                kind = "h" if "k_conv<32, 0>" in name else ("o" if "k_conv<16, 1>" in name else "x")
+                d = disp.setdefault((f, int(row["Dispatch_Id"])), [kind, 0.0])
+                d[1] += float(row["Counter_Value"])
+    seq = [disp[k] for k in sorted(disp)]
+    return [sum(v for _, v in seq[i:i + 6]) for i in range(len(seq) - 5)
+            if [k for k, _ in seq[i:i + 6]] == ["h"] * 5 + ["o"]]
+
+
 def run_traffic(args):
     """HBM bytes per launch of every hot-path kernel from two rocprofv3
     counter passes of `--workload kernels` (FETCH_SIZE, then WRITE_SIZE, KiB
     per dispatch), each scaled by what the same counter reads for the
     library's streaming copy of 1 GiB each way; written to
-    profiles/traffic.json with the hash of the kernel sources."""
+    profiles/traffic.json with the hash of the kernel sources.  With
+    --pmc-net-fetch / --pmc-net-write (the same two passes of `--workload
+    network`), also the bytes of one forward pass of the warm-start network,
+    scaled by the same factors."""
     import statistics
     fetch = read_pmc(args.pmc_fetch, "FETCH_SIZE")
     write = read_pmc(args.pmc_write, "WRITE_SIZE")
@@ -663,6 +704,15 @@ def run_traffic(args):
     out = {"n%d" % args.n: res,
            "calibration": {"kernel": "adr::k_stream_copy", "bytes_each_way": int(gib),
                            "fetch_factor": ff, "write_factor": wf}}
+    if args.pmc_net_fetch and args.pmc_net_write:
+        nf = statistics.median(read_forward_pmc(args.pmc_net_fetch, "FETCH_SIZE")) * 1024.0 * ff
+        nw = statistics.median(read_forward_pmc(args.pmc_net_write, "WRITE_SIZE")) * 1024.0 * wf
+        nodes = 64 * 258 * 258
+        out["network_258_b64"] = dict(bytes_per_forward=round(nf + nw), fetch_bytes=round(nf), write_bytes=round(nw),
+                                      algorithmic_bytes=nodes * (10 * 2 + 5 * 32 * 2 + 5 * 32 * 2 + 4),
+                                      bytes_per_node=round((nf + nw) / nodes, 2), source_hash=network_source_hash())
+        lines.append("network  FETCH %.1f MB  WRITE %.1f MB per forward pass (64 x 258 x 258 nodes) = %.1f B per node "
+                     "(algorithmic 664)" % (nf / 1e6, nw / 1e6, (nf + nw) / nodes))
     path = os.path.join(ROOT, "profiles", "traffic.json")
     old = {}
     if os.path.exists(path):
