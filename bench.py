@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-RING_NAMES = {0: "deep", 1: "compact", 2: "paired"}   # adr_sweep_ring
+RING_NAMES = {0: "deep", 1: "compact"}   # adr_sweep_ring
 
 
 def kernel_bytes(precision="fp64", tables=True):
