@@ -371,10 +371,12 @@ size_t adr_device_bytes(const adr_problem *p);
 adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
 
 /* Ring of the 31-row sweeps: -1 automatic (the default), 0 one workgroup per
- * CU with a deep LDS ring, 1 two per CU with a four-slot ring (used where a
- * tile holds at most three arrays: the L sweeps and the table-driven U sweep;
- * the U sweep reading the diagonals keeps the deep ring).  Results do not
- * depend on it.  ADR_ERR_ARG for another mode.  For tuning and tests. */
+ * CU with a deep LDS ring, 1 a four-slot ring small enough for two per CU
+ * (with three loader waves instead of five where the strips fit one per CU;
+ * used where a tile holds at most three arrays: the L sweeps and the
+ * table-driven U sweep; the U sweep reading the diagonals keeps the deep
+ * ring).  Results do not depend on it.  ADR_ERR_ARG for another mode.  For
+ * tuning and tests. */
 adr_status adr_set_sweep_ring(adr_problem *p, int32_t mode);
 
 /* The ring the 31-row sweeps use now: 0 deep, 1 compact. */
