@@ -219,7 +219,11 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) acc[r][mb] = acc0[mb];
-    // taps outside, rows inside: 4 MB independent accumulations in flight
+    // taps outside, rows inside: 4 MB independent accumulations in flight.
+    // The products run at raised issue priority, so that a wave in this
+    // phase gets its matrix instructions issued while the other workgroup's
+    // wave on the SIMD is in its VALU-bound epilogue.
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int tp = 0; tp < 9; ++tp) {
       const int dy = tp / 3, dx = tp % 3;
@@ -232,6 +236,7 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[r][mb] = mfma(wa[tp][mb], bv[r], acc[r][mb]);
     }
+    __builtin_amdgcn_s_setprio(0);
     // lane holds channels mb*16 + 4q + i of node (row, px)
     uint16_t *so = &s_out[wv][0];
 #pragma unroll
