@@ -81,6 +81,7 @@ def parse():
                     default="single")
     ap.add_argument("--pmc-fetch", default="", help="traffic: rocprofv3 output folder of the FETCH_SIZE pass")
     ap.add_argument("--pmc-write", default="", help="traffic: rocprofv3 output folder of the WRITE_SIZE pass")
+    ap.add_argument("--instances-out", default="", help="batch: write the per-instance outcomes to this JSON file")
     ap.add_argument("--pmc-net-fetch", default="", help="traffic: FETCH_SIZE folder of --workload network")
     ap.add_argument("--pmc-net-write", default="", help="traffic: WRITE_SIZE folder of --workload network")
     ap.add_argument("--large-maxit", type=int, default=10000, help="large: pass limit of the Dirichlet solves")
@@ -301,9 +302,9 @@ def run_batch(args):
         "sweep_ring": RING_NAMES.get(rows[1], str(rows[1])),
         "cpu_baseline": cpu,
     }
-    with open(os.path.join(ROOT, "gpurun_out", "batch_instances.json") if os.path.isdir(
-            os.path.join(ROOT, "gpurun_out")) else os.devnull, "w") as fh:
-        json.dump(per_instance, fh)
+    if args.instances_out:
+        with open(args.instances_out, "w") as fh:
+            json.dump(per_instance, fh)
     print(json.dumps(out), flush=True)
 
 
