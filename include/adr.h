@@ -292,7 +292,7 @@ adr_status adr_batch_solve(adr_problem *p, double tol, int32_t maxit, const doub
                            double *x_dev, double *hist_l2, double *hist_max, adr_solve_info *info);
 
 /* Sweep-schedule autotuner: times M^{-1} on the problem's right-hand sides
- * for every supported schedule -- 15-row strips, and 31-row strips with one
+ * for every supported schedule -- 16-row strips, and 32-row strips with one
  * workgroup per CU (deep LDS ring) or two (compact ring) -- keeps the fastest
  * and returns its strip height (and the time of one application in ms).
  * Needs adr_ilu0 / adr_batch_ilu0 first; results do not depend on the choice. */
@@ -362,15 +362,15 @@ adr_status adr_dot_noalloc(const double *x_dev, const double *y_dev, int64_t n, 
 /* Bytes of device memory the problem holds (after ilu0 / solve buffers). */
 size_t adr_device_bytes(const adr_problem *p);
 
-/* Sweep geometry: rows per strip (R = 15 or 31) for the wavefront kernels,
- * or 0 for the default (31, also the height a new problem starts with).
- * Also returns 31-row strips to the automatic ring choice (the compact ring
+/* Sweep geometry: rows per strip (R = 16 or 32) for the wavefront kernels,
+ * or 0 for the default (32, also the height a new problem starts with).
+ * Also returns 32-row strips to the automatic ring choice (the compact ring
  * while the strips fit one per CU or once they exceed 1.5 per CU -- 384 on
  * 256 CUs -- the deep ring in between).  Results do not depend on it.  For
  * tuning and tests. */
 adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
 
-/* Ring of the 31-row sweeps: -1 automatic (the default), 0 one workgroup per
+/* Ring of the 32-row sweeps: -1 automatic (the default), 0 one workgroup per
  * CU with a deep LDS ring, 1 a four-slot ring small enough for two per CU
  * (with three loader waves instead of five where the strips fit one per CU;
  * used where a tile holds at most three arrays: the L sweeps and the
@@ -379,7 +379,7 @@ adr_status adr_set_sweep_rows(adr_problem *p, int32_t rows);
  * tuning and tests. */
 adr_status adr_set_sweep_ring(adr_problem *p, int32_t mode);
 
-/* The ring the 31-row sweeps use now: 0 deep, 1 compact. */
+/* The ring the 32-row sweeps use now: 0 deep, 1 compact. */
 int32_t adr_sweep_ring(const adr_problem *p);
 
 /* Stencil tables.  The off-diagonals of the operator of Section 4 are

@@ -199,7 +199,7 @@ class Problem(_Workspace):
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
 
     def set_sweep_ring(self, mode):
-        """31-row sweep ring: -1 automatic, 0 deep (one workgroup per CU), 1 compact (two)."""
+        """32-row sweep ring: -1 automatic, 0 deep (one workgroup per CU), 1 compact (two)."""
         _lib.check(_lib.load().adr_set_sweep_ring(self._h, int(mode)))
 
     @property
@@ -395,7 +395,7 @@ class Batch(_Workspace):
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
 
     def set_sweep_ring(self, mode):
-        """31-row sweep ring: -1 automatic, 0 deep (one workgroup per CU), 1 compact (two)."""
+        """32-row sweep ring: -1 automatic, 0 deep (one workgroup per CU), 1 compact (two)."""
         _lib.check(_lib.load().adr_set_sweep_ring(self._h, int(mode)))
 
     @property

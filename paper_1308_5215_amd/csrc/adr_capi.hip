@@ -116,10 +116,10 @@ std::mutex g_scratch_mu;
 constexpr int MAX_DEVICES = 64;
 double2 *g_scratch[MAX_DEVICES] = {};
 
-// Strip height used until the autotuner or the caller picks one: 31 rows
-// (measured faster than 15 for every square grid from 128^2 to 4096^2: half
+// Strip height used until the autotuner or the caller picks one: 32 rows
+// (measured faster than 16 for every square grid from 128^2 to 4096^2: half
 // as many strip hand-offs for one more chunk of lag each).
-int default_rows(int /*max_ny*/) { return 31; }
+int default_rows(int /*max_ny*/) { return 32; }
 
 }  // namespace
 
@@ -148,7 +148,7 @@ struct adr_problem {
   int *d_sorder = nullptr;   // instances in strip-ticket order
   int64_t ntot = 0;            // unknowns over the batch
   int nblk = 0, nstrips = 0, rows = 0, max_ny = 0;
-  int compact = -1;            // 31-row sweep ring: -1 automatic, 0 deep, 1 compact
+  int compact = -1;            // 32-row sweep ring: -1 automatic, 0 deep, 1 compact
   int cus = 256;               // compute units of the device
   size_t bytes = 0;
   // matrix (batched)
@@ -215,7 +215,7 @@ struct adr_problem {
 #ifdef ADR_NO_XCD_GROUPS
     return 0;
 #else
-    if (count != 1 || ring_compact() || rows != 31 || nstrips > cus) return 0;
+    if (count != 1 || ring_compact() || rows != 32 || nstrips > cus) return 0;
     return (nstrips + 7) / 8;
 #endif
   }
@@ -250,7 +250,7 @@ void pfree(adr_problem *P, T *&p) {
 // Hand-off words for the smallest strip height of every instance.
 int64_t handoff_words(const adr_problem *P) {
   int64_t words = 0;
-  for (int k = 0; k < P->count; ++k) words += (int64_t)((P->ny[k] + 14) / 15) * P->nx[k];
+  for (int k = 0; k < P->count; ++k) words += (int64_t)((P->ny[k] + 15) / 16) * P->nx[k];
   return words;
 }
 
@@ -828,7 +828,7 @@ adr_status adr_get_factors(const adr_problem *P, double *lw, double *ls, double 
 adr_status adr_set_sweep_rows(adr_problem *P, int32_t rows) {
   g_last_error.clear();
   if (!P) return fail(ADR_ERR_ARG, "problem is NULL");
-  if (rows != 0 && rows != 15 && rows != 31) return fail(ADR_ERR_ARG, "rows must be 0, 15 or 31 (got %d)", rows);
+  if (rows != 0 && rows != 16 && rows != 32) return fail(ADR_ERR_ARG, "rows must be 0, 16 or 32 (got %d)", rows);
   P->compact = -1;
   return set_rows(P, rows ? rows : default_rows(P->max_ny));
 }
@@ -991,8 +991,8 @@ adr_status adr_autotune(adr_problem *P, int32_t *rows_chosen, double *ms_per_app
   if (st == ADR_OK) st = ensure_events(P);
   if (st != ADR_OK) return st;
   // time M^{-1} applied to the batch's right-hand sides for every strip
-  // schedule: 15-row strips, 31-row strips with the deep ring, with the compact one
-  const int cand[][2] = {{15, -1}, {31, 0}, {31, 1}};
+  // schedule: 16-row strips, 32-row strips with the deep ring, with the compact one
+  const int cand[][2] = {{16, -1}, {32, 0}, {32, 1}};
   int best = P->rows, best_cmp = P->compact;
   float best_ms = -1.f;
   hipEvent_t e0 = P->ev0, e1 = P->ev1;

@@ -82,7 +82,7 @@ struct BatchGeom {
   int nblk;           // total streaming blocks
   int nstrips;        // total strips
   int rows;           // strip height R
-  int compact;        // 31-row sweeps: 0 deep ring; 1 compact ring (76 KB, two workgroups per CU);
+  int compact;        // 32-row sweeps: 0 deep ring; 1 compact ring (76 KB, two workgroups per CU);
                       // 2 compact ring with three loader waves (strips at most one per CU)
   int xcd_group;      // > 0: strips by workgroup index, xcd_group consecutive strips per XCD
   const int *sorder;  // device: instances in strip-ticket order (largest work first); strip0 ascends along it
@@ -166,7 +166,7 @@ hipError_t launch_max_error(const MaxErrArgs &a, const Stream1D &g, hipStream_t 
 // dst[k] = src[k], k < n: a plain streaming copy (bandwidth reference).
 hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, int blocks, hipStream_t s);
 
-// Wavefront kernels.  rows = strip height R (15 or 31).
+// Wavefront kernels.  rows = strip height R (16 or 32).
 struct Factors64 {
   double *lw, *ls, *invd;
 };

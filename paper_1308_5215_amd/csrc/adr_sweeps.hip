@@ -16,6 +16,10 @@
 //     memory, one relaxed agent-scope atomic per value, with a sentinel
 //     meaning "not yet written"), with coefficients chosen so that its
 //     result is exactly the published value.
+// Strip heights are multiples of the chunk width W = 16 (R = 16 or 32): the
+// strip's last row then covers, in each chunk, exactly the 16 columns of one
+// chunk of the strip above, which can start two chunks behind -- the same lag
+// as R = 15 or 31 with one more row per strip.
 // Coefficients and right-hand sides are brought in by coalesced loads of
 // skewed R x W tiles into registers two chunks ahead, transposed through LDS,
 // and the results leave the same way.  Strips start in ticket order, so a
@@ -42,7 +46,7 @@ constexpr unsigned SPIN_LIMIT = 1u << 20;   // polls before a wait is declared f
 #define ADR_LOADER_DEPTH 2
 #endif
 // chunks of loads in flight per loader wave: two where one workgroup holds
-// the CU (31-row strips, deep ring: 256 registers per wave), one where two
+// the CU (32-row strips, deep ring: 256 registers per wave), one where two
 // workgroups share it (128 registers per wave)
 constexpr int LDEPTH_DEEP = ADR_LOADER_DEPTH;
 
@@ -222,10 +226,10 @@ struct SweepShape {
   static constexpr int PITCH = W + 2;               // 16-byte aligned rows
   static constexpr int NT = NTH;                    // threads per workgroup
   static constexpr int NLD = NT / 64 - 3;           // loader waves
-  // 76 KB (two workgroups per CU) for R = 15 and for compact 31-row strips
+  // 76 KB (two workgroups per CU) for R = 16 and for compact 32-row strips
   // (tiles of at most three arrays, four or more slots), else 150 KB (one
   // workgroup per CU, a deeper ring)
-  static constexpr int LDS_BUDGET = (R <= 15 || CMP) ? 76 * 1024 : 150 * 1024;
+  static constexpr int LDS_BUDGET = (R <= 16 || CMP) ? 76 * 1024 : 150 * 1024;
   static constexpr int OUT_BYTES = 2 * L * PITCH * 8;
   static constexpr int CHUNK_BYTES = NIN * L * PITCH * CTB;
   static constexpr int NC_FIT = (LDS_BUDGET - OUT_BYTES) / CHUNK_BYTES;
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(NTH, CMP ? 4 : 1) void k_sweep_ws(SweepParams p) {
   using Sh = SweepShape<R, NL, (int)sizeof(CT), CMP, NTH>;
   constexpr int W = Sh::W, L = Sh::L, PITCH = Sh::PITCH, NC = Sh::NC, NT = Sh::NT, NLD = Sh::NLD;
   constexpr int RPP = Sh::RPP, NP = Sh::NP;
-  constexpr int LDEPTH = (R > 15 && !CMP) ? LDEPTH_DEEP : 1;
+  constexpr int LDEPTH = (R > 16 && !CMP) ? LDEPTH_DEEP : 1;
   static_assert(L <= 64, "strip too tall");
   __shared__ __align__(16) CT s_in[NC][NL][L][PITCH];
   __shared__ __align__(16) double s_out[2][L][PITCH];
@@ -910,14 +914,14 @@ hipError_t launch_ilu0(const Dia &A, const BatchGeom &g, Factors64 f64, Factors3
   p.sync = sync;
   p.bad = (unsigned long long *)bad;
   switch (g.rows) {
-    case 15: hipLaunchKernelGGL((k_ilu0<15, 32>), dim3(g.nstrips), dim3(64), 0, s, p); break;
-    case 31: hipLaunchKernelGGL((k_ilu0<31, 32>), dim3(g.nstrips), dim3(64), 0, s, p); break;
+    case 16: hipLaunchKernelGGL((k_ilu0<16, 32>), dim3(g.nstrips), dim3(64), 0, s, p); break;
+    case 32: hipLaunchKernelGGL((k_ilu0<32, 32>), dim3(g.nstrips), dim3(64), 0, s, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-// Compact 31-row strips (two workgroups per CU, a four-slot ring) pay off when
+// Compact 32-row strips (two workgroups per CU, a four-slot ring) pay off when
 // the strips outnumber the CUs well (batches); a grid whose strips about fill
 // the CUs keeps the deeper ring.  Tiles of four arrays (the U sweep reading
 // the diagonals) always take the deep ring.
@@ -926,18 +930,18 @@ static hipError_t launch_sweep_t(const SweepParams &p, hipStream_t s) {
   constexpr bool CAN_CMP = OP == 0 || TAB;   // three arrays per tile
   const int grid = p.g.xcd_group > 0 ? 8 * p.g.xcd_group : p.g.nstrips;
   switch (p.g.rows) {
-    case 15:
-      hipLaunchKernelGGL((k_sweep_ws<15, OP, PREC, TAB, false, ADR_SWEEP_THREADS>), dim3(p.g.nstrips),
+    case 16:
+      hipLaunchKernelGGL((k_sweep_ws<16, OP, PREC, TAB, false, ADR_SWEEP_THREADS>), dim3(p.g.nstrips),
                          dim3(ADR_SWEEP_THREADS), 0, s, p);
       break;
-    case 31:
+    case 32:
       if (CAN_CMP && p.g.compact == 2)   // compact ring, three loader waves
-        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, CAN_CMP, 384>), dim3(p.g.nstrips), dim3(384), 0, s, p);
+        hipLaunchKernelGGL((k_sweep_ws<32, OP, PREC, TAB, CAN_CMP, 384>), dim3(p.g.nstrips), dim3(384), 0, s, p);
       else if (CAN_CMP && p.g.compact)
-        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, CAN_CMP, ADR_SWEEP_THREADS>), dim3(p.g.nstrips),
+        hipLaunchKernelGGL((k_sweep_ws<32, OP, PREC, TAB, CAN_CMP, ADR_SWEEP_THREADS>), dim3(p.g.nstrips),
                            dim3(ADR_SWEEP_THREADS), 0, s, p);
       else
-        hipLaunchKernelGGL((k_sweep_ws<31, OP, PREC, TAB, false, ADR_SWEEP_THREADS>), dim3(grid),
+        hipLaunchKernelGGL((k_sweep_ws<32, OP, PREC, TAB, false, ADR_SWEEP_THREADS>), dim3(grid),
                            dim3(ADR_SWEEP_THREADS), 0, s, p);
       break;
 

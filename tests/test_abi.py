@@ -80,5 +80,5 @@ def test_schedule_settings_reject_a_missing_problem():
     L = _lib.load()
     assert L.adr_set_sweep_ring(None, 1) == _lib.ERR_ARG
     assert b"NULL" in L.adr_last_error()
-    assert L.adr_set_sweep_rows(None, 31) == _lib.ERR_ARG
+    assert L.adr_set_sweep_rows(None, 32) == _lib.ERR_ARG
     assert L.adr_sweep_ring(None) == 0

@@ -22,8 +22,8 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("name,key", [
-    ("void adr::k_sweep_ws<31, 0, 0, true, true, 384>(adr::SweepParams)", "lsweep"),
-    ("void adr::k_sweep_ws<15, 1, 2, false, false, 512>(adr::SweepParams)", "usweep"),
+    ("void adr::k_sweep_ws<32, 0, 0, true, true, 384>(adr::SweepParams)", "lsweep"),
+    ("void adr::k_sweep_ws<16, 1, 2, false, false, 512>(adr::SweepParams)", "usweep"),
     ("adr::k_pass_xr(adr::IterBufs, adr::BatchGeom)", "pass_xr"),
     ("adr::k_pass_xr_fin(adr::IterBufs, adr::BatchGeom)", None),
     ("void adr::k_pass_v<true>(adr::IterBufs, adr::BatchGeom)", "pass_v"),
@@ -49,7 +49,7 @@ def _write_pmc(folder, counter, rows):
 def test_traffic_summary_scales_by_the_copy_and_skips_idle_dispatches(tmp_path, monkeypatch, capsys):
     gib_kib = (1 << 30) / 1024.0
     copy = "adr::k_stream_copy(double __vector(2) const*, double __vector(2)*, long, long)"
-    lsw = "void adr::k_sweep_ws<31, 0, 0, true, true, 384>(adr::SweepParams)"
+    lsw = "void adr::k_sweep_ws<32, 0, 0, true, true, 384>(adr::SweepParams)"
     # the copy reads half its bytes by FETCH_SIZE (factor 2) and all of them by WRITE_SIZE (factor 1);
     # the sweep's second dispatch did no work (an instance that had stopped)
     _write_pmc(str(tmp_path / "f"), "FETCH_SIZE", [(1, copy, gib_kib / 2), (2, lsw, 1000.0), (3, lsw, 3.0),

@@ -93,10 +93,10 @@ def test_dot_bitwise(adr, n):
     assert adr.dot(cuda(x), cuda(y)) == orc.dot(x, y)
 
 
-@pytest.mark.parametrize("rows", [15, 31])
+@pytest.mark.parametrize("rows", [16, 32])
 @pytest.mark.parametrize("nx,ny,scheme,bc,eps", [
     (64, 64, 0, 0, 0.1), (37, 53, 1, 1, 2.0), (1, 40, 1, 0, 0.5), (45, 1, 0, 0, 0.5),
-    (130, 67, 1, 0, 0.01), (33, 140, 0, 1, 1.0), (200, 200, 1, 0, 0.05)])
+    (130, 67, 1, 0, 0.01), (33, 140, 0, 1, 1.0), (200, 200, 1, 0, 0.05), (50, 33, 0, 0, 0.2)])
 def test_ilu0_and_sweeps_bitwise(adr, rows, nx, ny, scheme, bc, eps):
     say("ilu0+sweeps", rows, nx, ny, scheme, bc, eps)
     prob = adr.assemble(eps, 1.0, 1.0, nx, ny, scheme, bc)
@@ -149,7 +149,7 @@ def test_solve_small_config_parity(adr, scheme):
     assert orc.max_error(P, x) == pytest.approx(orc.max_error(P, ref.x), rel=1e-6)
 
 
-@pytest.mark.parametrize("rows", [15, 31])
+@pytest.mark.parametrize("rows", [16, 32])
 @pytest.mark.parametrize("nx,ny,scheme,bc,eps,X,Y", [
     (127, 129, 0, 0, 0.01, 1.0, 1.0), (100, 80, 1, 1, 2.0, 1.0, 1.0), (257, 130, 1, 0, 0.05, 2.0, 1.0),
     (19, 19, 0, 1, 4.0, 4.0, 4.0), (5, 300, 1, 0, 0.2, 1.0, 1.0)])
@@ -439,7 +439,7 @@ def test_batch_workload_sampled_instances_match_oracle(adr):
         assert equal(host(xs[k]), ref.x)
 
 
-@pytest.mark.parametrize("rows", [15, 31])
+@pytest.mark.parametrize("rows", [16, 32])
 @pytest.mark.parametrize("precision", ["fp32_factors", "fp32_sweeps"])
 def test_mixed_precision_precond_bitwise(adr, rows, precision):
     """FP32-stored factors (rounded from the FP64 ILU(0)) applied with FP64
@@ -527,7 +527,7 @@ def fields_grf(nx, ny, X, Y, k):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_factors", "fp32_sweeps"])
 def test_sweep_ring_changes_no_bit(adr, precision):
-    """31-row strips with one workgroup per CU (deep LDS ring) or two (compact
+    """32-row strips with one workgroup per CU (deep LDS ring) or two (compact
     ring) give the same preconditioner and the same solve, bit for bit, with
     the stencil tables and with the full diagonals."""
     say("sweep ring", precision)
@@ -562,15 +562,19 @@ def test_batch_autotune_keeps_results(adr):
     r0 = b.solve(1e-10, 500)
     x0 = host(r0.x).copy()
     rows, ms = b.autotune()
-    assert rows in (15, 31) and ms > 0
+    assert rows in (16, 32) and ms > 0
     r1 = b.solve(1e-10, 500)
     assert np.array_equal(host(r1.x), x0)
     assert list(r1.iters) == list(r0.iters)
-    # both rings of the 31-row strips, forced
+    # both rings of the 32-row strips, forced
     for mode in (0, 1):
-        b.set_sweep_rows(31)
+        b.set_sweep_rows(32)
         b.set_sweep_ring(mode)
         assert b.sweep_ring == mode
         r2 = b.solve(1e-10, 500)
         assert np.array_equal(host(r2.x), x0)
         assert list(r2.iters) == list(r0.iters)
+    # strip heights are multiples of the 16-column chunk
+    for bad in (15, 31, 48):
+        with pytest.raises(adr.AdrError):
+            b.set_sweep_rows(bad)
