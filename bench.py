@@ -117,11 +117,38 @@ def kernel_us(prob, fns, reps):
     return {name: t * 1e3 / reps for name, t in total.items()}
 
 
+def code_text(path):
+    """A C/C++ source without its comments and with its white space collapsed:
+    what the compiler reads of it, so that editing a comment leaves counters
+    taken on the same code valid."""
+    with open(path, encoding="utf-8") as fh:
+        s = fh.read()
+    out, i, n = [], 0, len(s)
+    while i < n:
+        c = s[i]
+        if c in "\"'":                     # string or character literal, kept whole
+            j = i + 1
+            while j < n and s[j] != c:
+                j += 2 if s[j] == "\\" else 1
+            out.append(s[i:j + 1])
+            i = j + 1
+        elif s.startswith("//", i):
+            j = s.find("\n", i)
+            i = n if j < 0 else j
+        elif s.startswith("/*", i):
+            j = s.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def sweep_source_hash():
     h = hashlib.sha256()
     for f in ("adr_sweeps.hip", "adr_kernels.hip", "adr_device.h", "adr_internal.h"):
-        with open(os.path.join(ROOT, "paper_1308_5215_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        h.update(code_text(os.path.join(ROOT, "paper_1308_5215_amd", "csrc", f)).encode())
     return h.hexdigest()[:16]
 
 
@@ -636,8 +663,7 @@ def read_pmc(folder, counter):
 
 def network_source_hash():
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1308_5215_amd", "csrc", "adr_cnn.hip"), "rb") as fh:
-        h.update(fh.read())
+    h.update(code_text(os.path.join(ROOT, "paper_1308_5215_amd", "csrc", "adr_cnn.hip")).encode())
     return h.hexdigest()[:16]
 
 

@@ -204,8 +204,9 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvArgs a) {
   }
   fetch(t, pre);
   put(0, pre);
-  // step for tile t from LDS half `buf`: tile t + G is fetched into
-  // registers while it runs and put into the other half afterwards
+  // step for tile t from LDS half `buf`: the workgroup's next tile (t +
+  // stride) is fetched into registers while it runs and put into the other
+  // half afterwards
   auto step = [&](int buf) {
     const int tn = t + stride;
     if (tn < t_hi) fetch(tn, pre);

@@ -93,3 +93,15 @@ def test_forward_pass_counters_are_summed_per_forward(tmp_path):
     rows.append((d, o, 100.0))
     _write_pmc(str(tmp_path / "n"), "FETCH_SIZE", rows)
     assert bench.read_forward_pmc(str(tmp_path / "n"), "FETCH_SIZE") == [25.0, 25.0]
+
+
+def test_source_hash_ignores_comments_and_layout(tmp_path):
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    c = tmp_path / "c.hip"
+    a.write_text('int f(int x) {  // the lane\'s value\n  return x + 1; /* one\n more */ }\nconst char *s = "a // b";\n')
+    b.write_text('// header\nint f(int x) {\n  return x + 1;\n}\nconst char *s = "a // b";   /* kept string */\n')
+    c.write_text('int f(int x) { return x + 2; }\nconst char *s = "a // b";\n')
+    assert bench.code_text(str(a)) == bench.code_text(str(b))
+    assert bench.code_text(str(a)) != bench.code_text(str(c))
+    assert '"a // b"' in bench.code_text(str(a))       # a string that looks like a comment stays
