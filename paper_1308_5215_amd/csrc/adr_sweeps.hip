@@ -18,7 +18,7 @@
 //     result is exactly the published value.
 // Strip heights are multiples of the chunk width W = 16 (R = 16 or 32): the
 // strip's last row then covers, in each chunk, exactly the 16 columns of one
-// chunk of the strip above, which can start two chunks behind -- the same lag
+// chunk of the next strip, which can start two chunks behind -- the same lag
 // as R = 15 or 31 with one more row per strip.
 // Coefficients and right-hand sides are brought in by coalesced loads of
 // skewed R x W tiles into registers two chunks ahead, transposed through LDS,
