@@ -196,6 +196,7 @@ class Problem(_Workspace):
         return z
 
     def set_sweep_rows(self, rows):
+        """Strip height of the wavefront kernels: 16 or 32 rows (0: the default, 32)."""
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
 
     def set_sweep_ring(self, mode):
@@ -392,6 +393,7 @@ class Batch(_Workspace):
         return rows.value, ms.value
 
     def set_sweep_rows(self, rows):
+        """Strip height of the wavefront kernels: 16 or 32 rows (0: the default, 32)."""
         _lib.check(_lib.load().adr_set_sweep_rows(self._h, int(rows)))
 
     def set_sweep_ring(self, mode):
